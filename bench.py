@@ -1,0 +1,287 @@
+"""Benchmark of the HoSZp hot path on one MI355X.
+
+Workload: the 3-D 512^3 float32 Kolmogorov-spectrum random field (two seeded
+fields A and B, 537 MB each) at relative error bounds 1e-2, 1e-3 and 1e-4 of
+A's value range, block 32.  One step runs, for every bound, the whole hot
+path on device-resident data through the C ABI (async entry points, one
+stream):
+
+    compress A, compress B, mean(A), decompress(B), variance(A), negate(B),
+    add(A, B), mul(A, 3.14)
+
+The ops are ordered so consecutive ops read different streams (the 256 MB
+last-level cache is refilled by the large float32 traffic in between).  After
+the timed steps the decompress-then-compute workflow (decompress, float32 op
+in HBM, re-compress for compression-as-output ops) is timed the same way for
+the comparison, and the CPU oracle is timed on a bounded sample.
+
+stdout: one JSON line.  Diagnostics go to stderr.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "homomorphic op GB/s (raw-equiv) vs decompress+op; compress/decompress GB/s"
+HBM_PEAK_GBS = 8000.0
+RELS = (1e-2, 1e-3, 1e-4)
+BLOCK = 32
+SCALAR = 3.14
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=512, help="edge of the cubic field")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 24,
+                    help="elements of each field the oracle is timed on (0 = skip)")
+    ap.add_argument("--trad-reps", type=int, default=3)
+    return ap.parse_args()
+
+
+class Timer:
+    """HIP events on the current stream around one enqueued op."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.pairs = {}
+
+    def run(self, key, fn):
+        s = self.torch.cuda.Event(enable_timing=True)
+        e = self.torch.cuda.Event(enable_timing=True)
+        s.record()
+        fn()
+        e.record()
+        self.pairs.setdefault(key, []).append((s, e))
+
+    def mean_us(self, key):
+        ps = self.pairs[key]
+        return 1000.0 * sum(s.elapsed_time(e) for s, e in ps) / len(ps)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the library has no "
+              "multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2408_11971_amd as hz
+    import synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    ctx = hz.context(0)
+    n3 = args.n
+    N = n3 ** 3
+    log(f"generating two {n3}^3 fields on the GPU")
+    A = synth.grf_3d(n3, seed=3, device=dev).view(-1)
+    B = synth.grf_3d(n3, seed=4, device=dev).view(-1)
+    rng = synth.value_range(A)
+    ebs = [rel * rng for rel in RELS]
+    cap = hz.compress_bound(N, BLOCK)
+    bufs = {}
+    for i, _ in enumerate(ebs):
+        for k in ("a", "b", "neg", "sum", "mul", "trad"):
+            bufs[(i, k)] = torch.empty(cap, dtype=torch.uint8, device=dev)
+    dec = torch.empty(N, dtype=torch.float32, device=dev)
+    d2 = torch.empty(N, dtype=torch.float32, device=dev)
+    t32 = torch.empty(N, dtype=torch.float32, device=dev)
+    res = {name: hz.new_result(dev) for name in
+           ("ca", "cb", "mean", "dec", "var", "neg", "add", "mul", "t0", "t1", "t2")}
+
+    def step(tm):
+        for i, eb in enumerate(ebs):
+            ca, cb = bufs[(i, "a")], bufs[(i, "b")]
+            tm.run((i, "compress"), lambda: hz.compress_async(A, eb, BLOCK, ca, res["ca"], ctx))
+            tm.run((i, "compress_b"), lambda: hz.compress_async(B, eb, BLOCK, cb, res["cb"], ctx))
+            tm.run((i, "mean"), lambda: hz.mean_async(ca, res["mean"], ctx))
+            tm.run((i, "decompress"), lambda: hz.decompress_async(cb, dec, res["dec"], ctx))
+            tm.run((i, "variance"), lambda: hz.variance_async(ca, res["var"], ctx))
+            tm.run((i, "negate"), lambda: hz.negate_async(cb, bufs[(i, "neg")], res["neg"], ctx))
+            tm.run((i, "add"), lambda: hz.add_async(ca, cb, bufs[(i, "sum")], res["add"], ctx))
+            tm.run((i, "mul"), lambda: hz.mul_async(ca, SCALAR, bufs[(i, "mul")], res["mul"], ctx))
+
+    def check(name):
+        r = hz.read_result(res[name], ctx)
+        if r["code"] != 0:
+            raise RuntimeError(f"{name} failed with code {r['code']}")
+        return r
+
+    log("warmup")
+    for _ in range(args.warmup):
+        step(Timer(torch))
+    torch.cuda.synchronize()
+    for name in ("ca", "cb", "mean", "dec", "var", "neg", "add", "mul"):
+        check(name)
+
+    tm = Timer(torch)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(tm)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = 1000.0 * wall / args.steps
+    for name in ("ca", "cb", "mean", "dec", "var", "neg", "add", "mul"):
+        check(name)
+
+    # sizes of the streams of every bound (from the last step's result records)
+    sizes = []
+    for i, eb in enumerate(ebs):
+        hz.compress_async(A, eb, BLOCK, bufs[(i, "a")], res["ca"], ctx)
+        hz.compress_async(B, eb, BLOCK, bufs[(i, "b")], res["cb"], ctx)
+        ca_b = check("ca")["out_bytes"]
+        cb_b = check("cb")["out_bytes"]
+        hz.add_async(bufs[(i, "a")], bufs[(i, "b")], bufs[(i, "sum")], res["add"], ctx)
+        hz.negate_async(bufs[(i, "b")], bufs[(i, "neg")], res["neg"], ctx)
+        hz.mul_async(bufs[(i, "a")], SCALAR, bufs[(i, "mul")], res["mul"], ctx)
+        cz_b = check("add")["out_bytes"]
+        cn_b = check("neg")["out_bytes"]
+        cm_b = check("mul")["out_bytes"]
+        h = hz.header_of(bufs[(i, "a")])
+        nb = h["nb"]
+        w = bufs[(i, "a")][64:64 + nb].to(torch.int32)
+        nonconst = int((w > 0).sum().item())
+        sizes.append({"ca": ca_b, "cb": cb_b, "sum": cz_b, "neg": cn_b, "mul": cm_b, "nb": nb,
+                      "nonconst": nonconst, "payload": h["payload_bytes"]})
+
+    # ---- decompress-then-compute workflow
+    log("timing the decompress-then-compute workflow")
+    tt = Timer(torch)
+    for _ in range(args.trad_reps):
+        for i, eb in enumerate(ebs):
+            ca, cb, ct = bufs[(i, "a")], bufs[(i, "b")], bufs[(i, "trad")]
+
+            def t_mean():
+                hz.decompress_async(ca, dec, res["t0"], ctx)
+                hz.f32_mean_async(dec, res["t1"], ctx)
+
+            def t_var():
+                hz.decompress_async(ca, dec, res["t0"], ctx)
+                hz.f32_variance_async(dec, res["t1"], ctx)
+
+            def t_add():
+                hz.decompress_async(ca, dec, res["t0"], ctx)
+                hz.decompress_async(cb, d2, res["t1"], ctx)
+                hz.f32_add_async(dec, d2, t32, ctx)
+                hz.compress_async(t32, eb, BLOCK, ct, res["t2"], ctx)
+
+            def t_neg():
+                hz.decompress_async(cb, dec, res["t0"], ctx)
+                hz.f32_negate_async(dec, t32, ctx)
+                hz.compress_async(t32, eb, BLOCK, ct, res["t2"], ctx)
+
+            def t_mul():
+                hz.decompress_async(ca, dec, res["t0"], ctx)
+                hz.f32_mul_async(dec, SCALAR, t32, ctx)
+                hz.compress_async(t32, eb, BLOCK, ct, res["t2"], ctx)
+
+            for key, fn in (("mean", t_mean), ("variance", t_var), ("add", t_add),
+                            ("negate", t_neg), ("mul", t_mul)):
+                tt.run((i, key), fn)
+    torch.cuda.synchronize()
+    for name in ("t0", "t1", "t2"):
+        check(name)
+
+    # ---- per-op figures
+    ops = {}
+    raw_per_step = 0
+    busiest = None
+    for i, rel in enumerate(RELS):
+        sz = sizes[i]
+        C, Cb = sz["ca"], sz["cb"]
+        red_bytes = sz["nb"] + 4 * sz["nb"] + 4 * sz["nonconst"] + sz["payload"]
+        table = {
+            "compress": (4 * N, 4 * N + C, tm.mean_us((i, "compress"))),
+            "decompress": (4 * N, Cb + 4 * N, tm.mean_us((i, "decompress"))),
+            "mean": (4 * N, red_bytes, tm.mean_us((i, "mean"))),
+            "variance": (4 * N, red_bytes, tm.mean_us((i, "variance"))),
+            "negate": (4 * N, 2 * Cb, tm.mean_us((i, "negate"))),
+            "add": (8 * N, C + Cb + sz["sum"], tm.mean_us((i, "add"))),
+            "mul": (4 * N, C + sz["mul"], tm.mean_us((i, "mul"))),
+        }
+        raw_per_step += sum(v[0] for v in table.values()) + 4 * N  # + compress of B
+        row = {"cr": round(4 * N / C, 3), "const_block_pct": round(100.0 * (1 - sz["nonconst"] / sz["nb"]), 2)}
+        for op, (raw, alg, us) in table.items():
+            entry = {"us": round(us, 2), "gbps_raw": round(raw / us / 1e3, 1),
+                     "hbm_gbps": round(alg / us / 1e3, 1),
+                     "hbm_frac": round(alg / us / 1e3 / HBM_PEAK_GBS, 4)}
+            if op in ("mean", "variance", "negate", "add", "mul"):
+                trad = tt.mean_us((i, op))
+                entry["trad_us"] = round(trad, 2)
+                entry["speedup_vs_trad"] = round(trad / us, 2)
+            row[op] = entry
+            total = us * (2 if op == "compress" else 1)
+            if busiest is None or total > busiest[0]:
+                busiest = (total, op, rel, alg, us)
+        ops[f"rel{rel:g}"] = row
+
+    value = raw_per_step / (ms_per_step / 1000.0) / 1e9
+    _, bop, brel, balg, bus = busiest
+    achieved = balg / bus / 1e3
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": bop, "rel_eb": brel, "bytes_per_launch": balg,
+                "us_per_launch": round(bus, 2)}
+
+    cpu = None
+    if args.cpu_sample > 0:
+        cpu = cpu_baseline(A, B, ebs, min(args.cpu_sample, N))
+
+    line = {
+        "metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32 bins (f64 quantization, int64/int128 sums)", "data": "synthetic",
+        "config": {"workload": f"grf3d_{n3}^3_k-5/3_two_fields", "n": N, "block": BLOCK,
+                   "rel_eb": list(RELS), "ops_per_step": 8 * len(RELS),
+                   "raw_bytes_per_step": raw_per_step, "parallelism": "single_gpu"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "ops": ops,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(A, B, ebs, n):
+    """The oracle, single-threaded, on the first n elements of both fields."""
+    import numpy as np
+
+    from oracle import ref
+
+    a = A[:n].cpu().numpy()
+    b = B[:n].cpu().numpy()
+    log(f"timing the CPU oracle on {n} elements per field")
+    raw = 0
+    t0 = time.perf_counter()
+    for eb in ebs:
+        ca = ref.compress(a, eb, BLOCK)
+        cb = ref.compress(b, eb, BLOCK)
+        ref.mean(ca)
+        ref.decompress(cb)
+        ref.variance(ca)
+        ref.negate(cb)
+        ref.add(ca, cb)
+        ref.mul(ca, SCALAR)
+        raw += 4 * n * 9
+    sec = time.perf_counter() - t0
+    return {"value": round(raw / sec / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {n} elements of each 512^3 field, the 8 ops of a step at all 3 "
+                      f"bounds ({sec:.1f} s)"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,215 @@
+/*
+ * hoszp.h -- C ABI of the MI355X (gfx950) HoSZp library.
+ *
+ * HoSZp (Agarwal et al., arXiv 2408.11971) is an error-bounded lossy
+ * compressor whose compressed form supports arithmetic without full
+ * decompression.  This library implements its data-parallel path on one GPU:
+ *   compression        Sec. IV-A: quantization (Eq. 3), 1-D Lorenzo with the
+ *                      block's first bin split off as the outlier (Eq. 4),
+ *                      sign split, blockwise fixed-length bit packing, and the
+ *                      section order of Fig. 3;
+ *   decompression      the inverse of all steps (Fig. 2 caption);
+ *   homomorphic ops    Sec. V / Table II: negation (workflow 1), element-wise
+ *                      addition (workflow 2), scalar multiplication, mean and
+ *                      variance (workflow 3).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - `d_*` arguments are device pointers owned by the caller (for instance a
+ *   torch tensor's data pointer); the library never frees them and never keeps
+ *   them after the call returns.  Host pointers are named `h_*` or are plain
+ *   output scalars.
+ * - `stream` is a hipStream_t passed as `void*` (NULL = the null stream).
+ *   Every kernel of a call runs on that stream, in order.
+ * - Return value: a HOSZP_* status code, 0 on success.  Synchronous calls
+ *   (those with host outputs such as `out_bytes`, `mean`) block on `stream`
+ *   and report errors the kernels detected; on any error the contents of the
+ *   output buffers are unspecified.
+ * - `*_async` variants only enqueue work.  They write their outcome into a
+ *   caller-owned device record `hoszp_result` (status bit mask, output size,
+ *   scalar result) and never synchronize, so they can be chained and captured
+ *   in a hipGraph.  Arguments checkable on the host are still checked before
+ *   anything is enqueued (the call then returns the error and enqueues
+ *   nothing).
+ * - A context owns the device scratch the kernels use (look-back status words,
+ *   tile tickets, reduction accumulators).  Calls that share a context must not
+ *   run concurrently (use one stream per context, or one context per stream).
+ * - Streams are self-describing: the 64-byte header carries n, the block size
+ *   and the error bound, so decoders take no shape arguments.
+ * - Limits: 1 <= n <= 2^32 - 1 elements; block size 32, 64 or 128; the error
+ *   bound `eb` is absolute, finite and > 0; quantization bins must lie in
+ *   [-(2^31 - 1), 2^31 - 1].  Float input pointers must be 16-byte aligned;
+ *   stream pointers 16-byte aligned.
+ *
+ * Stream layout (little-endian)
+ * -----------------------------
+ *   header (64 B): "HOSZ", u16 version 1, u16 flags 0, u32 block, u32 0,
+ *                  u64 n, f64 eb, u64 nb (= ceil(n / block)),
+ *                  u64 payload_bytes, u64 total_bytes, u64 0
+ *   W  nb bytes           width of every block (0 = constant block)
+ *   O  4 nb bytes         outlier (first bin) of every block, int32
+ *   S  nb block/8 bytes   sign bits, slot k of a block at bit 7-(k%8) of its
+ *                         byte k/8; 1 = negative delta
+ *   P  payload_bytes      every block's `block` magnitudes at the block's
+ *                         width, most significant bit first, blocks in order
+ *   Each section starts at the next 16-byte boundary; padding bytes are 0.
+ */
+#ifndef HOSZP_H
+#define HOSZP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define HOSZP_OK 0
+#define HOSZP_ERR_ARG 1       /* invalid argument (null pointer, eb <= 0, block, n, alignment) */
+#define HOSZP_ERR_NONFINITE 2 /* NaN or Inf in the input field */
+#define HOSZP_ERR_RANGE 3     /* a result bin leaves [-(2^31-1), 2^31-1] */
+#define HOSZP_ERR_FORMAT 4    /* malformed, truncated or inconsistent stream */
+#define HOSZP_ERR_MISMATCH 5  /* add: operands differ in n, block size or eb */
+#define HOSZP_ERR_CAPACITY 6  /* output buffer too small */
+#define HOSZP_ERR_DEVICE 7    /* a HIP runtime call failed */
+#define HOSZP_ERR_NOMEM 8     /* device or pinned allocation failed */
+
+/* Outcome of an asynchronous call, written by the GPU into caller-owned
+ * device memory (64 bytes, 8-byte aligned).
+ *   status     bit (1 << code) set for every error the kernels detected;
+ *              0 = success.  hoszp_status_code() picks the reported code.
+ *   out_bytes  size of the produced stream (compress, negate, add, mul).
+ *   value      mean or variance (mean, variance). */
+typedef struct hoszp_result {
+  uint32_t status;
+  uint32_t reserved0;
+  uint64_t out_bytes;
+  double value;
+  uint64_t reserved[5];
+} hoszp_result;
+
+/* Host-side view of a stream header. */
+typedef struct hoszp_info {
+  uint64_t n;
+  uint32_t block;
+  uint32_t version;
+  double eb;
+  uint64_t nb;
+  uint64_t payload_bytes;
+  uint64_t total_bytes;
+} hoszp_info;
+
+typedef struct hoszp_ctx hoszp_ctx;
+
+/* Create a context on HIP device `device` (allocates its scratch, about
+ * 13 MB of device memory plus one pinned host record).  Returns HOSZP_OK and
+ * sets *out, or HOSZP_ERR_DEVICE / HOSZP_ERR_NOMEM. */
+int hoszp_ctx_create(int device, hoszp_ctx** out);
+
+/* Release a context (waits for nothing: the caller must have synchronized
+ * every stream that used it). NULL is accepted. */
+int hoszp_ctx_destroy(hoszp_ctx* ctx);
+
+/* Worst-case stream size for n elements (every block at width 32); 0 when n or
+ * block is invalid.  Output buffers of compress/add/mul must be at least this
+ * large. */
+size_t hoszp_compress_bound(uint64_t n, uint32_t block);
+
+/* Parse a stream header held in host memory (`header_bytes` >= 64).  Checks the
+ * magic, version, block size, n, nb, eb and section sizes; the widths are not
+ * visible here and are checked by the kernels. */
+int hoszp_parse_header(const void* h_header, size_t header_bytes, hoszp_info* out);
+
+/* Map a status bit mask (hoszp_result.status) to one code, by precedence
+ * ARG, FORMAT, MISMATCH, CAPACITY, NONFINITE, RANGE. */
+int hoszp_status_code(uint32_t status_mask);
+
+/* Human-readable name of a status code. */
+const char* hoszp_strerror(int code);
+
+/* ---- compression (Sec. IV-A) ------------------------------------------- */
+
+/* Compress n float32 values at absolute error bound eb with `block` elements
+ * per block into d_out (capacity out_cap >= hoszp_compress_bound(n, block)).
+ * *out_bytes receives the stream size.  Every decompressed value lies within
+ * eb of its input (plus float32 rounding of the reconstruction). */
+int hoszp_compress(hoszp_ctx* ctx, const float* d_x, uint64_t n, double eb, uint32_t block,
+                   void* d_out, size_t out_cap, size_t* out_bytes, void* stream);
+int hoszp_compress_async(hoszp_ctx* ctx, const float* d_x, uint64_t n, double eb,
+                         uint32_t block, void* d_out, size_t out_cap, hoszp_result* d_res,
+                         void* stream);
+
+/* Full decompression: d_x[i] = (float)((double)bin_i * 2 eb) for the stream's
+ * n elements; n_cap is the capacity of d_x in elements (>= n). */
+int hoszp_decompress(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, float* d_x,
+                     uint64_t n_cap, void* stream);
+int hoszp_decompress_async(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, float* d_x,
+                           uint64_t n_cap, hoszp_result* d_res, void* stream);
+
+/* ---- homomorphic operations (Sec. V) ----------------------------------- */
+
+/* Negation (Sec. V-A-1, workflow 1): every outlier negated and, in every
+ * non-constant block, the sign bits of its valid slots inverted; widths and
+ * payload are copied.  out_cap >= the input's total size.  d_out may equal
+ * d_c (in place).  The decoded result is exactly the negated field. */
+int hoszp_negate(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, void* d_out, size_t out_cap,
+                 size_t* out_bytes, void* stream);
+int hoszp_negate_async(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, void* d_out,
+                       size_t out_cap, hoszp_result* d_res, void* stream);
+
+/* Element-wise addition (Sec. V-C-1, workflow 2): outliers added, signed
+ * deltas added, then widths, signs and bits re-derived.  Both operands must
+ * have the same n, block size and bitwise-equal eb (else MISMATCH); a sum bin
+ * outside the bin range gives RANGE.  The output is the canonical stream of
+ * the summed bins.  d_out must not overlap the inputs. */
+int hoszp_add(hoszp_ctx* ctx, const void* d_a, size_t a_bytes, const void* d_b, size_t b_bytes,
+              void* d_out, size_t out_cap, size_t* out_bytes, void* stream);
+int hoszp_add_async(hoszp_ctx* ctx, const void* d_a, size_t a_bytes, const void* d_b,
+                    size_t b_bytes, void* d_out, size_t out_cap, hoszp_result* d_res,
+                    void* stream);
+
+/* Scalar multiplication (Sec. V-A-4, workflow 3): bins decoded, replaced by
+ * floor(s * bin + 1/2) computed exactly, then re-encoded.  s must be finite;
+ * a result outside the bin range gives RANGE.  d_out must not overlap d_c. */
+int hoszp_mul(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, double s, void* d_out,
+              size_t out_cap, size_t* out_bytes, void* stream);
+int hoszp_mul_async(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, double s, void* d_out,
+                    size_t out_cap, hoszp_result* d_res, void* stream);
+
+/* Mean (Sec. V-B-1): ((double)S / n) * 2 eb with S the exact int64 sum of
+ * the bins. */
+int hoszp_mean(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, double* mean, void* stream);
+int hoszp_mean_async(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, hoszp_result* d_res,
+                     void* stream);
+
+/* Population variance (Sec. V-B-2): ((double)(n Q - S^2) / n / n) * (2 eb)^2
+ * with S and Q = sum of squared bins held exactly (128-bit). */
+int hoszp_variance(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, double* var, void* stream);
+int hoszp_variance_async(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, hoszp_result* d_res,
+                         void* stream);
+
+/* ---- decompress-then-compute path (the comparison workflow) ------------ */
+
+/* Float32 operations on decompressed fields, used to time the traditional
+ * workflow (Sec. VI-B, Fig. 4a): y = -x, y = a + b, y = (float)(s * x) over n
+ * elements, and the float64 mean / population variance of x.  Results of the
+ * reductions land in d_res->value. */
+int hoszp_f32_negate_async(hoszp_ctx* ctx, const float* d_x, float* d_y, uint64_t n, void* stream);
+int hoszp_f32_add_async(hoszp_ctx* ctx, const float* d_a, const float* d_b, float* d_y,
+                        uint64_t n, void* stream);
+int hoszp_f32_mul_async(hoszp_ctx* ctx, const float* d_x, double s, float* d_y, uint64_t n,
+                        void* stream);
+int hoszp_f32_mean_async(hoszp_ctx* ctx, const float* d_x, uint64_t n, hoszp_result* d_res,
+                         void* stream);
+int hoszp_f32_variance_async(hoszp_ctx* ctx, const float* d_x, uint64_t n, hoszp_result* d_res,
+                             void* stream);
+
+/* Block until `stream` is idle and return the code of a result record that
+ * an async call filled (also copying it to *h_out when h_out is not NULL). */
+int hoszp_result_wait(hoszp_ctx* ctx, const hoszp_result* d_res, hoszp_result* h_out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

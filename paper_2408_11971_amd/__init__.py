@@ -1,0 +1,363 @@
+"""HoSZp on MI355X: error-bounded compression and homomorphic operations on the
+compressed stream (Agarwal et al., arXiv 2408.11971), as gfx950 HIP kernels
+behind the C ABI of ``include/hoszp.h``.
+
+This module is argument marshalling only: torch supplies device memory and
+streams, every step of compression, decompression and the homomorphic
+operations runs in ``libhoszp.so``.  Importing works anywhere; the first call
+that needs the library raises ``HoszpUnavailable`` if it has not been built
+(``python -m paper_2408_11971_amd.build``) -- there is no CPU fallback.
+"""
+import ctypes
+import os
+import struct
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhoszp.so")
+
+OK, ERR_ARG, ERR_NONFINITE, ERR_RANGE, ERR_FORMAT, ERR_MISMATCH, ERR_CAPACITY, ERR_DEVICE, \
+    ERR_NOMEM = range(9)
+RESULT_BYTES = 64
+
+
+class HoszpUnavailable(RuntimeError):
+    pass
+
+
+class HoszpError(RuntimeError):
+    def __init__(self, code, where):
+        msg = _lib().hoszp_strerror(code).decode() if _LIB is not None else str(code)
+        super().__init__(f"{where}: {msg} (code {code})")
+        self.code = code
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_uint32), ("reserved0", ctypes.c_uint32),
+                ("out_bytes", ctypes.c_uint64), ("value", ctypes.c_double),
+                ("reserved", ctypes.c_uint64 * 5)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint64), ("block", ctypes.c_uint32), ("version", ctypes.c_uint32),
+                ("eb", ctypes.c_double), ("nb", ctypes.c_uint64),
+                ("payload_bytes", ctypes.c_uint64), ("total_bytes", ctypes.c_uint64)]
+
+
+_LIB = None
+_VP, _SZ, _U64, _U32, _DBL, _INT = (ctypes.c_void_p, ctypes.c_size_t, ctypes.c_uint64,
+                                    ctypes.c_uint32, ctypes.c_double, ctypes.c_int)
+_SIGNATURES = {
+    "hoszp_ctx_create": (_INT, [_INT, ctypes.POINTER(_VP)]),
+    "hoszp_ctx_destroy": (_INT, [_VP]),
+    "hoszp_compress_bound": (_SZ, [_U64, _U32]),
+    "hoszp_parse_header": (_INT, [_VP, _SZ, ctypes.POINTER(Info)]),
+    "hoszp_status_code": (_INT, [_U32]),
+    "hoszp_strerror": (ctypes.c_char_p, [_INT]),
+    "hoszp_compress": (_INT, [_VP, _VP, _U64, _DBL, _U32, _VP, _SZ, ctypes.POINTER(_SZ), _VP]),
+    "hoszp_compress_async": (_INT, [_VP, _VP, _U64, _DBL, _U32, _VP, _SZ, _VP, _VP]),
+    "hoszp_decompress": (_INT, [_VP, _VP, _SZ, _VP, _U64, _VP]),
+    "hoszp_decompress_async": (_INT, [_VP, _VP, _SZ, _VP, _U64, _VP, _VP]),
+    "hoszp_negate": (_INT, [_VP, _VP, _SZ, _VP, _SZ, ctypes.POINTER(_SZ), _VP]),
+    "hoszp_negate_async": (_INT, [_VP, _VP, _SZ, _VP, _SZ, _VP, _VP]),
+    "hoszp_add": (_INT, [_VP, _VP, _SZ, _VP, _SZ, _VP, _SZ, ctypes.POINTER(_SZ), _VP]),
+    "hoszp_add_async": (_INT, [_VP, _VP, _SZ, _VP, _SZ, _VP, _SZ, _VP, _VP]),
+    "hoszp_mul": (_INT, [_VP, _VP, _SZ, _DBL, _VP, _SZ, ctypes.POINTER(_SZ), _VP]),
+    "hoszp_mul_async": (_INT, [_VP, _VP, _SZ, _DBL, _VP, _SZ, _VP, _VP]),
+    "hoszp_mean": (_INT, [_VP, _VP, _SZ, ctypes.POINTER(_DBL), _VP]),
+    "hoszp_mean_async": (_INT, [_VP, _VP, _SZ, _VP, _VP]),
+    "hoszp_variance": (_INT, [_VP, _VP, _SZ, ctypes.POINTER(_DBL), _VP]),
+    "hoszp_variance_async": (_INT, [_VP, _VP, _SZ, _VP, _VP]),
+    "hoszp_f32_negate_async": (_INT, [_VP, _VP, _VP, _U64, _VP]),
+    "hoszp_f32_add_async": (_INT, [_VP, _VP, _VP, _VP, _U64, _VP]),
+    "hoszp_f32_mul_async": (_INT, [_VP, _VP, _DBL, _VP, _U64, _VP]),
+    "hoszp_f32_mean_async": (_INT, [_VP, _VP, _U64, _VP, _VP]),
+    "hoszp_f32_variance_async": (_INT, [_VP, _VP, _U64, _VP, _VP]),
+    "hoszp_result_wait": (_INT, [_VP, _VP, ctypes.POINTER(Result), _VP]),
+}
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise HoszpUnavailable(
+                f"{LIB_PATH} is missing: build it with `python -m paper_2408_11971_amd.build`")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = lib
+    return _LIB
+
+
+def exported_symbols():
+    """Names of the C entry points this binding wraps (all must be exported)."""
+    return sorted(_SIGNATURES)
+
+
+def _check(rc, where):
+    if rc != OK:
+        raise HoszpError(rc, where)
+
+
+# ---------------------------------------------------------------- host-only
+
+def compress_bound(n: int, block: int = 32) -> int:
+    return _lib().hoszp_compress_bound(n, block)
+
+
+def parse_header(header: bytes) -> dict:
+    buf = ctypes.create_string_buffer(bytes(header[:64]), 64)
+    info = Info()
+    _check(_lib().hoszp_parse_header(ctypes.cast(buf, _VP), len(header), ctypes.byref(info)),
+           "parse_header")
+    return {k: getattr(info, k) for k, _ in Info._fields_}
+
+
+def status_code(mask: int) -> int:
+    return _lib().hoszp_status_code(mask)
+
+
+# ---------------------------------------------------------------- contexts
+
+class Context:
+    """A library context on one device (owns the kernels' scratch)."""
+
+    def __init__(self, device: int = 0):
+        self.device = device
+        h = _VP()
+        _check(_lib().hoszp_ctx_create(device, ctypes.byref(h)), "ctx_create")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None) and _LIB is not None:
+            _LIB.hoszp_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_CTX = {}
+
+
+def context(device=None) -> Context:
+    import torch
+
+    dev = torch.cuda.current_device() if device is None else int(device)
+    if dev not in _CTX:
+        _CTX[dev] = Context(dev)
+    return _CTX[dev]
+
+
+def _stream(stream=None):
+    import torch
+
+    s = torch.cuda.current_stream() if stream is None else stream
+    return _VP(s.cuda_stream)
+
+
+def _ptr(t):
+    return _VP(t.data_ptr())
+
+
+def _nbytes(t):
+    return t.numel() * t.element_size()
+
+
+def new_result(device=None):
+    """A device-resident result record for the *_async calls."""
+    import torch
+
+    return torch.zeros(RESULT_BYTES // 8, dtype=torch.int64, device=device or "cuda")
+
+
+def read_result(res, ctx=None, stream=None) -> dict:
+    """Wait for `stream` and return the record as a dict (status code decoded)."""
+    ctx = ctx or context(res.device.index)
+    r = Result()
+    code = _lib().hoszp_result_wait(ctx.handle, _ptr(res), ctypes.byref(r), _stream(stream))
+    return {"code": code, "status": r.status, "out_bytes": r.out_bytes, "value": r.value}
+
+
+def header_of(c) -> dict:
+    """Parse the header of a device-resident stream (copies 64 bytes to host)."""
+    return parse_header(bytes(c[:64].cpu().numpy().tobytes()))
+
+
+def _out_stream(n, block, device):
+    import torch
+
+    cap = compress_bound(n, block)
+    if cap == 0:
+        raise HoszpError(ERR_ARG, "compress_bound")
+    return torch.empty(cap, dtype=torch.uint8, device=device)
+
+
+# ---------------------------------------------------------------- sync API
+
+def compress(x, eb: float, block: int = 32, out=None, stream=None):
+    """Compress a float32 CUDA tensor; returns the stream as a uint8 tensor
+    (a view of `out` trimmed to the stream size)."""
+    ctx = context(x.device.index)
+    x = x.contiguous().view(-1)
+    if out is None:
+        out = _out_stream(x.numel(), block, x.device)
+    nb = _SZ(0)
+    _check(_lib().hoszp_compress(ctx.handle, _ptr(x), x.numel(), float(eb), block, _ptr(out),
+                                 _nbytes(out), ctypes.byref(nb), _stream(stream)), "compress")
+    return out[:nb.value]
+
+
+def decompress(c, out=None, stream=None):
+    import torch
+
+    ctx = context(c.device.index)
+    n = header_of(c)["n"]
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=c.device)
+    _check(_lib().hoszp_decompress(ctx.handle, _ptr(c), _nbytes(c), _ptr(out), out.numel(),
+                                   _stream(stream)), "decompress")
+    return out[:n]
+
+
+def negate(c, out=None, stream=None):
+    import torch
+
+    ctx = context(c.device.index)
+    if out is None:
+        out = torch.empty_like(c)
+    nb = _SZ(0)
+    _check(_lib().hoszp_negate(ctx.handle, _ptr(c), _nbytes(c), _ptr(out), _nbytes(out),
+                               ctypes.byref(nb), _stream(stream)), "negate")
+    return out[:nb.value]
+
+
+def add(a, b, out=None, stream=None):
+    ctx = context(a.device.index)
+    if out is None:
+        h = header_of(a)
+        out = _out_stream(h["n"], h["block"], a.device)
+    nb = _SZ(0)
+    _check(_lib().hoszp_add(ctx.handle, _ptr(a), _nbytes(a), _ptr(b), _nbytes(b), _ptr(out),
+                            _nbytes(out), ctypes.byref(nb), _stream(stream)), "add")
+    return out[:nb.value]
+
+
+def mul(c, s: float, out=None, stream=None):
+    ctx = context(c.device.index)
+    if out is None:
+        h = header_of(c)
+        out = _out_stream(h["n"], h["block"], c.device)
+    nb = _SZ(0)
+    _check(_lib().hoszp_mul(ctx.handle, _ptr(c), _nbytes(c), float(s), _ptr(out), _nbytes(out),
+                            ctypes.byref(nb), _stream(stream)), "mul")
+    return out[:nb.value]
+
+
+def mean(c, stream=None) -> float:
+    ctx = context(c.device.index)
+    v = _DBL(0.0)
+    _check(_lib().hoszp_mean(ctx.handle, _ptr(c), _nbytes(c), ctypes.byref(v), _stream(stream)),
+           "mean")
+    return v.value
+
+
+def variance(c, stream=None) -> float:
+    ctx = context(c.device.index)
+    v = _DBL(0.0)
+    _check(_lib().hoszp_variance(ctx.handle, _ptr(c), _nbytes(c), ctypes.byref(v),
+                                 _stream(stream)), "variance")
+    return v.value
+
+
+# ---------------------------------------------------------------- async API
+# Enqueue only; outcomes land in a device result record (see new_result()).
+
+def compress_async(x, eb, block, out, res, ctx=None, stream=None):
+    ctx = ctx or context(x.device.index)
+    _check(_lib().hoszp_compress_async(ctx.handle, _ptr(x), x.numel(), float(eb), block,
+                                       _ptr(out), _nbytes(out), _ptr(res), _stream(stream)),
+           "compress_async")
+
+
+def decompress_async(c, out, res, ctx=None, stream=None, c_bytes=None):
+    ctx = ctx or context(c.device.index)
+    _check(_lib().hoszp_decompress_async(ctx.handle, _ptr(c), c_bytes or _nbytes(c), _ptr(out),
+                                         out.numel(), _ptr(res), _stream(stream)),
+           "decompress_async")
+
+
+def negate_async(c, out, res, ctx=None, stream=None, c_bytes=None):
+    ctx = ctx or context(c.device.index)
+    _check(_lib().hoszp_negate_async(ctx.handle, _ptr(c), c_bytes or _nbytes(c), _ptr(out),
+                                     _nbytes(out), _ptr(res), _stream(stream)), "negate_async")
+
+
+def add_async(a, b, out, res, ctx=None, stream=None, a_bytes=None, b_bytes=None):
+    ctx = ctx or context(a.device.index)
+    _check(_lib().hoszp_add_async(ctx.handle, _ptr(a), a_bytes or _nbytes(a), _ptr(b),
+                                  b_bytes or _nbytes(b), _ptr(out), _nbytes(out), _ptr(res),
+                                  _stream(stream)), "add_async")
+
+
+def mul_async(c, s, out, res, ctx=None, stream=None, c_bytes=None):
+    ctx = ctx or context(c.device.index)
+    _check(_lib().hoszp_mul_async(ctx.handle, _ptr(c), c_bytes or _nbytes(c), float(s), _ptr(out),
+                                  _nbytes(out), _ptr(res), _stream(stream)), "mul_async")
+
+
+def mean_async(c, res, ctx=None, stream=None, c_bytes=None):
+    ctx = ctx or context(c.device.index)
+    _check(_lib().hoszp_mean_async(ctx.handle, _ptr(c), c_bytes or _nbytes(c), _ptr(res),
+                                   _stream(stream)), "mean_async")
+
+
+def variance_async(c, res, ctx=None, stream=None, c_bytes=None):
+    ctx = ctx or context(c.device.index)
+    _check(_lib().hoszp_variance_async(ctx.handle, _ptr(c), c_bytes or _nbytes(c), _ptr(res),
+                                       _stream(stream)), "variance_async")
+
+
+def f32_negate_async(x, y, ctx=None, stream=None):
+    ctx = ctx or context(x.device.index)
+    _check(_lib().hoszp_f32_negate_async(ctx.handle, _ptr(x), _ptr(y), x.numel(), _stream(stream)),
+           "f32_negate_async")
+
+
+def f32_add_async(a, b, y, ctx=None, stream=None):
+    ctx = ctx or context(a.device.index)
+    _check(_lib().hoszp_f32_add_async(ctx.handle, _ptr(a), _ptr(b), _ptr(y), a.numel(),
+                                      _stream(stream)), "f32_add_async")
+
+
+def f32_mul_async(x, s, y, ctx=None, stream=None):
+    ctx = ctx or context(x.device.index)
+    _check(_lib().hoszp_f32_mul_async(ctx.handle, _ptr(x), float(s), _ptr(y), x.numel(),
+                                      _stream(stream)), "f32_mul_async")
+
+
+def f32_mean_async(x, res, ctx=None, stream=None):
+    ctx = ctx or context(x.device.index)
+    _check(_lib().hoszp_f32_mean_async(ctx.handle, _ptr(x), x.numel(), _ptr(res),
+                                       _stream(stream)), "f32_mean_async")
+
+
+def f32_variance_async(x, res, ctx=None, stream=None):
+    ctx = ctx or context(x.device.index)
+    _check(_lib().hoszp_f32_variance_async(ctx.handle, _ptr(x), x.numel(), _ptr(res),
+                                           _stream(stream)), "f32_variance_async")
+
+
+def result_struct_size() -> int:
+    return ctypes.sizeof(Result)
+
+
+def pack_header_fields(n, block, eb, payload, total):
+    """Header bytes for tests of the host-side parser."""
+    nb = (n + block - 1) // block
+    return struct.pack("<4sHHIIQdQQQQ", b"HOSZ", 1, 0, block, 0, n, eb, nb, payload, total, 0)

@@ -1,0 +1,119 @@
+// hoszp_internal.h -- definitions shared by the HIP kernels and the C-ABI
+// host code of the library (not installed, not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hoszp.h"
+
+namespace hz {
+
+// ---- stream format --------------------------------------------------------
+constexpr uint32_t kHeaderBytes = 64;
+constexpr uint32_t kMagic = 0x5A534F48u;  // "HOSZ" read as a little-endian u32
+constexpr int64_t kBinMax = 2147483647LL; // bins live in [-kBinMax, kBinMax]
+constexpr uint64_t kMaxN = 4294967295ULL; // n < 2^32
+
+// ---- work decomposition ---------------------------------------------------
+// A block of L slots is cut into L/32 "segments" of 32 slots.  Because every
+// block contributes L * width bits to the payload, segment s of a block owns
+// exactly `width` 32-bit words of it, starting on a word boundary, and sign
+// word s of the block.  Every kernel processes one segment per thread and a
+// tile of kTileSegs segments (8192 slots) per workgroup.
+constexpr int kThreads = 256;
+constexpr int kTileSegs = kThreads;
+constexpr int kTileWords = kTileSegs * 32;  // worst-case payload words of a tile
+
+// ---- status bits latched by the kernels (bit = 1 << code) -----------------
+constexpr uint32_t ST_ARG = 1u << HOSZP_ERR_ARG;
+constexpr uint32_t ST_NONFINITE = 1u << HOSZP_ERR_NONFINITE;
+constexpr uint32_t ST_RANGE = 1u << HOSZP_ERR_RANGE;
+constexpr uint32_t ST_FORMAT = 1u << HOSZP_ERR_FORMAT;
+constexpr uint32_t ST_MISMATCH = 1u << HOSZP_ERR_MISMATCH;
+constexpr uint32_t ST_CAPACITY = 1u << HOSZP_ERR_CAPACITY;
+
+// Section placement of a stream with n elements in blocks of L.
+struct Layout {
+  uint64_t n, nb, nseg, ntiles;
+  uint32_t L, spb;  // block size, segments per block
+  double eb;
+  uint64_t off_w, off_o, off_s, off_p;
+  uint64_t payload_bytes, total_bytes;
+};
+
+__host__ __device__ inline uint64_t round16(uint64_t x) { return (x + 15u) & ~uint64_t(15); }
+__host__ __device__ inline bool block_ok(uint32_t L) { return L == 32 || L == 64 || L == 128; }
+
+__host__ __device__ inline void place(Layout& g, uint64_t n, uint32_t L, double eb) {
+  g.n = n;
+  g.L = L;
+  g.spb = L / 32;
+  g.eb = eb;
+  g.nb = (n + L - 1) / L;
+  g.nseg = g.nb * g.spb;
+  g.ntiles = (g.nseg + kTileSegs - 1) / kTileSegs;
+  g.off_w = kHeaderBytes;
+  g.off_o = round16(g.off_w + g.nb);
+  g.off_s = round16(g.off_o + 4 * g.nb);
+  g.off_p = round16(g.off_s + 4 * g.nseg);
+  g.payload_bytes = 0;
+  g.total_bytes = g.off_p;
+}
+
+// Worst case: every block at width 32 (L words of payload per block).
+__host__ __device__ inline uint64_t bound_bytes(uint64_t n, uint32_t L) {
+  Layout g;
+  place(g, n, L, 1.0);
+  return g.off_p + 4 * uint64_t(L) * g.nb;
+}
+
+// Device scratch owned by a context.
+struct Scratch {
+  uint32_t* ctrl;       // [0] tile ticket, [1] finished-tile counter
+  uint64_t* acc;        // [0] S, [1] Q lo, [2] Q hi, [3] width sum
+  double* part;         // per-workgroup partials of the float32 reductions
+  uint64_t* st_a;       // look-back status words (input A / only input)
+  uint64_t* st_b;       // look-back status words (input B)
+  uint64_t* st_out;     // look-back status words (output stream)
+  uint32_t max_tiles;   // capacity of each status array
+  uint32_t max_part;    // capacity of `part`
+};
+
+// Scalar multiplier s = m * 2^-sh split on the host (see mul_split()).
+struct MulScalar {
+  int64_t m;    // |m| < 2^53
+  int32_t sh;   // shift in [1, 100]
+  int32_t big;  // 1 when |s| >= 2^52: any non-zero bin overflows
+};
+
+// Occupancy-derived persistent grid sizes, filled at context creation.
+struct Grids {
+  int compress, decode, add, mul, negate, f32;
+};
+
+// ---- launchers (kernels.hip) ----------------------------------------------
+hipError_t launch_init(const Scratch& s, hoszp_result* res, hipStream_t st);
+hipError_t launch_compress(const Scratch& s, const Grids& gr, const float* x, const Layout& g,
+                           double inv2e, uint8_t* out, uint32_t epoch, hoszp_result* res,
+                           hipStream_t st);
+hipError_t launch_decompress(const Scratch& s, const Grids& gr, const uint8_t* c,
+                             uint64_t c_bytes, float* x, uint64_t n_cap, uint32_t epoch,
+                             hoszp_result* res, hipStream_t st);
+hipError_t launch_reduce(const Scratch& s, const Grids& gr, const uint8_t* c, uint64_t c_bytes,
+                         bool variance, uint32_t epoch, hoszp_result* res, hipStream_t st);
+hipError_t launch_negate(const Scratch& s, const Grids& gr, const uint8_t* c, uint64_t c_bytes,
+                         uint8_t* out, uint64_t out_cap, hoszp_result* res, hipStream_t st);
+hipError_t launch_add(const Scratch& s, const Grids& gr, const uint8_t* a, uint64_t a_bytes,
+                      const uint8_t* b, uint64_t b_bytes, uint8_t* out, uint64_t out_cap,
+                      uint32_t epoch, hoszp_result* res, hipStream_t st);
+hipError_t launch_mul(const Scratch& s, const Grids& gr, const uint8_t* c, uint64_t c_bytes,
+                      MulScalar k, uint8_t* out, uint64_t out_cap, uint32_t epoch,
+                      hoszp_result* res, hipStream_t st);
+hipError_t launch_f32_unary(const Grids& gr, int op, const float* x, const float* y2, double s,
+                            float* out, uint64_t n, hipStream_t st);
+hipError_t launch_f32_reduce(const Scratch& s, const Grids& gr, const float* x, uint64_t n,
+                             bool variance, hoszp_result* res, hipStream_t st);
+hipError_t query_grids(Grids& gr, int num_cus);
+
+}  // namespace hz

@@ -1,0 +1,90 @@
+"""The C-ABI library loads on a machine without a GPU, exports every entry
+point ``include/hoszp.h`` declares, and its host-only functions agree with the
+oracle (no kernel launches here)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2408_11971_amd as hz
+from oracle import ref
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hoszp.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hoszp_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(hz.LIB_PATH):
+        from paper_2408_11971_amd import build
+        build.build()
+    return hz._lib()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 25
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(hz.exported_symbols())
+
+
+def test_result_record_is_64_bytes():
+    assert hz.result_struct_size() == 64 == hz.RESULT_BYTES
+
+
+@pytest.mark.parametrize("L", [32, 64, 128])
+def test_compress_bound_matches_oracle(lib, L):
+    for n in [1, 2, 31, 32, 33, 1000, 8191, 8192, 8193, 123457, 1 << 20, 2**32 - 1]:
+        assert hz.compress_bound(n, L) == ref.bound(n, L)
+
+
+def test_compress_bound_rejects_bad_args(lib):
+    assert hz.compress_bound(0, 32) == 0
+    assert hz.compress_bound(10, 16) == 0
+    assert hz.compress_bound(10, 256) == 0
+    assert hz.compress_bound(2**32, 32) == 0
+
+
+@pytest.mark.parametrize("L", [32, 64, 128])
+def test_parse_header_matches_oracle(lib, L):
+    x = np.random.default_rng(L).normal(0, 1, 5000).astype(np.float32)
+    c = ref.compress(x, 0.01, L)
+    info = ref.info(c)
+    h = hz.parse_header(c[:64].tobytes())
+    assert h["n"] == info["n"] and h["block"] == L and h["eb"] == info["eb"]
+    assert h["payload_bytes"] == info["payload_bytes"]
+    assert h["total_bytes"] == info["total_bytes"] == c.size
+
+
+def test_parse_header_rejects_corruption(lib):
+    c = ref.compress(np.zeros(100, np.float32), 0.5, 32)
+    for off, val in [(0, 0), (4, 2), (6, 1), (8, 48), (32, 9), (40, 5)]:
+        bad = c.copy()
+        bad[off] = val
+        with pytest.raises(hz.HoszpError) as e:
+            hz.parse_header(bad[:64].tobytes())
+        assert e.value.code == hz.ERR_FORMAT
+
+
+def test_status_precedence(lib):
+    bit = lambda code: 1 << code
+    assert hz.status_code(0) == hz.OK
+    assert hz.status_code(bit(hz.ERR_RANGE) | bit(hz.ERR_NONFINITE)) == hz.ERR_NONFINITE
+    assert hz.status_code(bit(hz.ERR_RANGE) | bit(hz.ERR_FORMAT)) == hz.ERR_FORMAT
+    assert hz.status_code(bit(hz.ERR_CAPACITY) | bit(hz.ERR_MISMATCH)) == hz.ERR_MISMATCH
+    assert hz.status_code(bit(hz.ERR_RANGE)) == hz.ERR_RANGE
+
+
+def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
+    monkeypatch.setattr(hz, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(hz, "_LIB", None)
+    with pytest.raises(hz.HoszpUnavailable):
+        hz.compress_bound(10, 32)

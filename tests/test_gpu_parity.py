@@ -1,0 +1,304 @@
+"""Parity of the gfx950 library (through the C ABI) with the CPU oracle.
+
+Streams and quantized values must be byte-identical, mean and variance equal
+to 1e-12 relative (they are computed from exact integer sums on both sides
+and are expected to be bit-identical).  Sizes span several 8192-slot tiles
+with ragged tails, every block size, and the degenerate cases of the method
+(constant blocks, single elements, partial blocks, extreme widths and bins).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import ref
+
+torch = pytest.importorskip("torch")
+import paper_2408_11971_amd as hz  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+BLOCKS = [32, 64, 128]
+REL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    return torch.device("cuda:0")
+
+
+def gpu(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def gaussian(n, seed, scale=1.0):
+    return np.random.default_rng(seed).normal(0.0, scale, n).astype(np.float32)
+
+
+def close(a, b, rel=REL):
+    return a == b or abs(a - b) <= rel * max(abs(a), abs(b))
+
+
+def check_all_ops(x, y, eb, L, dev, scalars=(3.14, -0.37)):
+    """compress/decompress/mean/variance/negate/add/mul parity for one case."""
+    xc = ref.compress(x, eb, L)
+    gx = gpu(x, dev)
+    c = hz.compress(gx, eb, L)
+    got = host(c)
+    assert got.size == xc.size
+    assert np.array_equal(got, xc), f"compress differs (n={x.size}, L={L}, eb={eb})"
+    assert np.array_equal(host(hz.decompress(c)), ref.decompress(xc))
+    assert close(hz.mean(c), ref.mean(xc))
+    assert close(hz.variance(c), ref.variance(xc))
+    assert np.array_equal(host(hz.negate(c)), ref.negate(xc))
+    if y is not None:
+        yc = ref.compress(y, eb, L)
+        cy = hz.compress(gpu(y, dev), eb, L)
+        assert np.array_equal(host(cy), yc)
+        assert np.array_equal(host(hz.add(c, cy)), ref.add(xc, yc))
+    for s in scalars:
+        assert np.array_equal(host(hz.mul(c, s)), ref.mul(xc, s)), f"mul by {s}"
+    return c, xc
+
+
+@pytest.mark.parametrize("L", BLOCKS)
+@pytest.mark.parametrize("n", [1, 2, 31, 32, 33, 63, 100, 255, 256, 257, 1000])
+def test_small_fields(dev, n, L):
+    print(f"case small n={n} L={L}", flush=True)
+    check_all_ops(gaussian(n, n), gaussian(n, n + 1), 0.01, L, dev)
+
+
+@pytest.mark.parametrize("L", BLOCKS)
+@pytest.mark.parametrize("n", [8191, 8192, 8193, 3 * 8192 + 77, (1 << 16) + 5, 200003])
+def test_multi_tile_ragged(dev, n, L):
+    print(f"case ragged n={n} L={L}", flush=True)
+    x = synth.sinusoid_1d(n, seed=1)
+    y = synth.sinusoid_1d(n, seed=2)
+    check_all_ops(x, y, synth.rel_eb(x, 1e-3), L, dev)
+
+
+@pytest.mark.parametrize("rel", [1e-2, 1e-3, 1e-4])
+def test_config_1d_full(dev, rel):
+    """2^20-element sum of 8 sinusoids plus noise, block 32."""
+    x = synth.sinusoid_1d(1 << 20, seed=1)
+    y = synth.sinusoid_1d(1 << 20, seed=2)
+    check_all_ops(x, y, synth.rel_eb(x, rel), 32, dev)
+
+
+@pytest.mark.parametrize("L", BLOCKS)
+def test_wide_fields(dev, L):
+    """Tiny bound: widths up to 30 bits (the 128-bit variance path)."""
+    x = gaussian(50000, 7)
+    y = gaussian(50000, 8)
+    c, xc = check_all_ops(x, y, 1e-8, L, dev, scalars=(0.5, -1.0))
+    widths = xc[64:64 + ref.info(xc)["n"] // L]
+    assert widths.max() >= 27
+
+
+@pytest.mark.parametrize("L", BLOCKS)
+def test_extreme_bins(dev, L):
+    """Bins near +-2^30 and deltas near 2^31: exact-range paths."""
+    rng = np.random.default_rng(11)
+    x = rng.uniform(-2.0**30, 2.0**30, 20000).astype(np.float32)
+    check_all_ops(x, None, 0.5, L, dev, scalars=(1.0, -1.0, 0.75))
+
+
+@pytest.mark.parametrize("L", BLOCKS)
+def test_constant_and_zero_fields(dev, L):
+    for x in (np.zeros(30000, np.float32), np.full(30000, 3.0, np.float32)):
+        c, xc = check_all_ops(x, x, 0.25, L, dev)
+        assert ref.info(xc)["payload_bytes"] == 0
+
+
+@pytest.mark.parametrize("L", BLOCKS)
+def test_climate_like_steps(dev, L):
+    steps = list(synth.climate_steps(2, 180, 360))
+    eb = synth.rel_eb(steps[0], 1e-4)
+    check_all_ops(steps[0], steps[1], eb, L, dev, scalars=(1.7320508, -0.5))
+
+
+def test_grf_3d_small(dev):
+    x = synth.grf_3d(48, seed=3)
+    y = synth.grf_3d(48, seed=4)
+    for rel in (1e-2, 1e-4):
+        check_all_ops(x.ravel(), y.ravel(), synth.rel_eb(x, rel), 32, dev)
+
+
+def test_add_negated_cancels(dev):
+    x = synth.sinusoid_1d(100000, 3)
+    c = hz.compress(gpu(x, dev), 1e-3, 32)
+    z = host(hz.add(c, hz.negate(c)))
+    info = ref.info(z)
+    assert info["payload_bytes"] == 0
+    assert np.all(ref.decode_bins(z) == 0)
+
+
+def test_negate_in_place(dev):
+    x = gaussian(70000, 5)
+    xc = ref.compress(x, 0.01, 64)
+    c = gpu(xc, dev)
+    out = hz.negate(c, out=c)
+    assert out.data_ptr() == c.data_ptr()
+    assert np.array_equal(host(c), ref.negate(xc))
+
+
+def test_repeatable_across_calls(dev):
+    """Look-back generations change every call; results must not."""
+    x = synth.sinusoid_1d(300000, 9)
+    gx = gpu(x, dev)
+    first = host(hz.compress(gx, 1e-3, 32))
+    for _ in range(20):
+        assert np.array_equal(host(hz.compress(gx, 1e-3, 32)), first)
+    c = gpu(first, dev)
+    means = {hz.mean(c) for _ in range(10)}
+    assert len(means) == 1
+
+
+# ------------------------------------------------------------------ errors
+
+def err_of(fn, *a, **k):
+    with pytest.raises(hz.HoszpError) as e:
+        fn(*a, **k)
+    return e.value.code
+
+
+def test_nonfinite_and_range_errors(dev):
+    for bad in (np.nan, np.inf, -np.inf):
+        x = gaussian(20000, 1)
+        x[12345] = bad
+        assert err_of(hz.compress, gpu(x, dev), 0.01, 32) == hz.ERR_NONFINITE
+    x = gaussian(20000, 1)
+    x[777] = 1e6
+    assert err_of(hz.compress, gpu(x, dev), 1e-4, 32) == hz.ERR_RANGE
+    x[778] = np.nan
+    assert err_of(hz.compress, gpu(x, dev), 1e-4, 32) == hz.ERR_NONFINITE
+
+
+def test_bad_arguments(dev):
+    x = gpu(gaussian(100, 1), dev)
+    for eb in (0.0, -1.0, math.inf, math.nan):
+        assert err_of(hz.compress, x, eb, 32) == hz.ERR_ARG
+    assert err_of(hz.compress, x, 0.1, 48) == hz.ERR_ARG
+    small = torch.empty(hz.compress_bound(100, 32) - 1, dtype=torch.uint8, device=dev)
+    assert err_of(hz.compress, x, 0.1, 32, out=small) == hz.ERR_CAPACITY
+    c = hz.compress(x, 0.1, 32)
+    assert err_of(hz.mul, c, math.inf) == hz.ERR_ARG
+
+
+def corruptions(c):
+    out = []
+    for off, val in [(0, ord("X")), (4, 2), (8, 48), (32, int(c[32]) + 1), (64, 33),
+                     (64, (int(c[64]) + 1) % 33)]:
+        d = c.copy()
+        d[off] = val
+        out.append(d)
+    out.append(c[:-4].copy())
+    return out
+
+
+def test_malformed_streams(dev):
+    x = synth.sinusoid_1d(50000, 4)
+    c = ref.compress(x, 1e-3, 32)
+    for bad in corruptions(c):
+        g = gpu(bad, dev)
+        assert err_of(hz.mean, g) == hz.ERR_FORMAT
+        assert err_of(hz.variance, g) == hz.ERR_FORMAT
+        assert err_of(hz.negate, g, out=torch.empty(c.size + 64, dtype=torch.uint8, device=dev)) \
+            == hz.ERR_FORMAT
+        out = torch.empty(hz.compress_bound(50000, 32), dtype=torch.uint8, device=dev)
+        assert err_of(hz.mul, g, 2.0, out=out) == hz.ERR_FORMAT
+        assert err_of(hz.add, g, gpu(c, dev), out=out) == hz.ERR_FORMAT
+        xo = torch.empty(50000, dtype=torch.float32, device=dev)
+        assert err_of(hz.decompress, g, out=xo) == hz.ERR_FORMAT
+
+
+def test_out_of_range_outlier_is_format_error(dev):
+    c = ref.compress(gaussian(1000, 3), 0.01, 32)
+    c[80:84] = np.array([0x80000000], dtype=np.uint32).view(np.uint8)
+    g = gpu(c, dev)
+    assert err_of(hz.mean, g) == hz.ERR_FORMAT
+    assert err_of(hz.variance, g) == hz.ERR_FORMAT
+
+
+def test_add_mismatch_capacity_and_range(dev):
+    a = gpu(ref.compress(gaussian(1000, 1), 0.01, 32), dev)
+    for other in (ref.compress(gaussian(1001, 1), 0.01, 32), ref.compress(gaussian(1000, 1), 0.01, 64),
+                  ref.compress(gaussian(1000, 1), 0.01 * (1 + 2**-52), 32)):
+        assert err_of(hz.add, a, gpu(other, dev)) == hz.ERR_MISMATCH
+    small = torch.empty(hz.compress_bound(1000, 32) - 1, dtype=torch.uint8, device=dev)
+    assert err_of(hz.add, a, a, out=small) == hz.ERR_CAPACITY
+    assert err_of(hz.mul, a, 2.0, out=small) == hz.ERR_CAPACITY
+    big = gpu(ref.encode_bins(np.full(100, 2**31 - 1, np.int32), 0.5, 32), dev)
+    assert err_of(hz.add, big, big) == hz.ERR_RANGE
+    assert err_of(hz.mul, big, 1.5) == hz.ERR_RANGE
+    assert err_of(hz.mul, big, 2.0**60) == hz.ERR_RANGE
+
+
+# ------------------------------------------------- decompress-then-compute
+
+def test_float32_workflow_ops(dev):
+    x = synth.sinusoid_1d(100003, 1)
+    y = synth.sinusoid_1d(100003, 2)
+    gx, gy = gpu(x, dev), gpu(y, dev)
+    out = torch.empty_like(gx)
+    hz.f32_negate_async(gx, out)
+    assert np.array_equal(host(out), -x)
+    hz.f32_add_async(gx, gy, out)
+    assert np.array_equal(host(out), x + y)
+    hz.f32_mul_async(gx, 1.7, out)
+    assert np.array_equal(host(out), (x.astype(np.float64) * 1.7).astype(np.float32))
+    res = hz.new_result(dev)
+    hz.f32_mean_async(gx, res)
+    m = hz.read_result(res)["value"]
+    assert close(m, float(np.mean(x.astype(np.float64))), 1e-12)
+    hz.f32_variance_async(gx, res)
+    v = hz.read_result(res)["value"]
+    assert close(v, float(np.var(x.astype(np.float64))), 1e-12)
+
+
+def test_traditional_equals_homomorphic(dev):
+    """Theorem 1 on the GPU: decompress + float32 op + compress gives the
+    same stream as the homomorphic op (negate, add), bins far below 2^24."""
+    x = synth.sinusoid_1d(1 << 18, 1)
+    y = synth.sinusoid_1d(1 << 18, 2)
+    eb = synth.rel_eb(x, 1e-3)
+    cx = hz.compress(gpu(x, dev), eb, 32)
+    cy = hz.compress(gpu(y, dev), eb, 32)
+    dx, dy = hz.decompress(cx), hz.decompress(cy)
+    t = torch.empty_like(dx)
+    hz.f32_add_async(dx, dy, t)
+    assert np.array_equal(host(hz.compress(t, eb, 32)), host(hz.add(cx, cy)))
+    hz.f32_negate_async(dx, t)
+    trad = host(hz.compress(t, eb, 32))
+    assert np.array_equal(ref.decode_bins(trad), ref.decode_bins(host(hz.negate(cx))))
+
+
+# ------------------------------------------------------------ async chain
+
+def test_async_chain_matches_sync(dev):
+    x = synth.sinusoid_1d(1 << 18, 5)
+    gx = gpu(x, dev)
+    eb = synth.rel_eb(x, 1e-3)
+    cap = hz.compress_bound(x.size, 32)
+    c = torch.empty(cap, dtype=torch.uint8, device=dev)
+    z = torch.empty(cap, dtype=torch.uint8, device=dev)
+    r1, r2, r3 = hz.new_result(dev), hz.new_result(dev), hz.new_result(dev)
+    hz.compress_async(gx, eb, 32, c, r1)
+    hz.mean_async(c, r2)
+    hz.add_async(c, c, z, r3)
+    a1, a2, a3 = hz.read_result(r1), hz.read_result(r2), hz.read_result(r3)
+    assert a1["code"] == a2["code"] == a3["code"] == 0
+    xc = ref.compress(x, eb, 32)
+    assert a1["out_bytes"] == xc.size
+    assert np.array_equal(host(c)[:xc.size], xc)
+    assert a2["value"] == ref.mean(xc)
+    zc = ref.add(xc, xc)
+    assert a3["out_bytes"] == zc.size
+    assert np.array_equal(host(z)[:zc.size], zc)
