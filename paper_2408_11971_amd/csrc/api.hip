@@ -1,10 +1,10 @@
 // api.hip -- host side of the C ABI declared in include/hoszp.h.
 //
-// Every entry point validates what the host can see, enqueues a small init
-// kernel (clears the context's tickets and accumulators and the result
-// record) and the operation's kernels on the caller's stream.  Synchronous
-// entry points then copy the 64-byte result record to pinned host memory and
-// wait for the stream.
+// Every entry point validates what the host can see and enqueues the
+// operation's kernels on the caller's stream; the operation's last kernel
+// fills the result record and returns the context's counters to zero.
+// Synchronous entry points then copy the 64-byte result record to pinned host
+// memory and wait for the stream.
 
 #include <math.h>
 #include <string.h>
@@ -53,8 +53,8 @@ int next_epoch(hoszp_ctx* ctx, hipStream_t st, uint32_t* epoch) {
   uint32_t e = (ctx->epoch + 1) & kEpochMask;
   if (e == 0) {
     e = 1;
-    const size_t bytes = size_t(3) * ctx->s.max_tiles * sizeof(uint64_t);
-    if (hipMemsetAsync(ctx->s.st_a, 0, bytes, st) != hipSuccess) return HOSZP_ERR_DEVICE;
+    const size_t bytes = size_t(ctx->s.max_tiles) * sizeof(uint64_t);
+    if (hipMemsetAsync(ctx->s.st_out, 0, bytes, st) != hipSuccess) return HOSZP_ERR_DEVICE;
   }
   ctx->epoch = e;
   *epoch = e;
@@ -62,6 +62,15 @@ int next_epoch(hoszp_ctx* ctx, hipStream_t st, uint32_t* epoch) {
 }
 
 int device_status(hipError_t e) { return e == hipSuccess ? HOSZP_OK : HOSZP_ERR_DEVICE; }
+
+// Status of an operation's launches; a failed launch can leave the context
+// counters mid-operation, so they are cleared before reporting the error.
+int launched(hoszp_ctx* ctx, hoszp_result* d_res, hipStream_t st, hipError_t e) {
+  if (e == hipSuccess) return HOSZP_OK;
+  (void)hipGetLastError();
+  (void)hz::launch_reset(ctx->s, d_res, st);
+  return HOSZP_ERR_DEVICE;
+}
 
 int wait_result(hoszp_ctx* ctx, const hoszp_result* d_res, hoszp_result* h_out, hipStream_t st) {
   if (hipMemcpyAsync(ctx->h_res, d_res, sizeof(hoszp_result), hipMemcpyDeviceToHost, st) !=
@@ -166,9 +175,14 @@ int hoszp_ctx_create(int device, hoszp_ctx** out) {
     delete ctx;
     return HOSZP_ERR_DEVICE;
   }
-  const size_t st_bytes = size_t(kMaxTiles) * sizeof(uint64_t);
-  const size_t bytes = 256 /* ctrl */ + 256 /* acc */ + size_t(kMaxPart) * sizeof(double) +
-                       3 * st_bytes + 2 * sizeof(hoszp_result);
+  auto up = [](size_t b) { return (b + 255) / 256 * 256; };  // every array 256-byte aligned
+  const size_t nchunk = kMaxTiles / hz::kChunkTiles + 2;
+  const size_t ctrl_b = 256, acc_b = 256, part_b = up(size_t(kMaxPart) * sizeof(double));
+  const size_t st_b = up(size_t(kMaxTiles) * sizeof(uint64_t));
+  const size_t off_b = up(nchunk * sizeof(uint64_t)), tw_b = up(size_t(kMaxTiles) * sizeof(uint32_t));
+  const size_t cw_b = up(nchunk * sizeof(uint32_t));
+  const size_t idx_b = off_b + tw_b + cw_b;
+  const size_t bytes = ctrl_b + acc_b + part_b + st_b + 2 * idx_b + up(sizeof(hoszp_result));
   if (hipMalloc(&ctx->d_mem, bytes) != hipSuccess) {
     delete ctx;
     return HOSZP_ERR_NOMEM;
@@ -179,15 +193,22 @@ int hoszp_ctx_create(int device, hoszp_ctx** out) {
     delete ctx;
     return HOSZP_ERR_NOMEM;
   }
-  uint8_t* p = static_cast<uint8_t*>(ctx->d_mem);
-  ctx->s.ctrl = reinterpret_cast<uint32_t*>(p);
-  ctx->s.acc = reinterpret_cast<uint64_t*>(p + 256);
-  ctx->s.part = reinterpret_cast<double*>(p + 512);
-  uint8_t* q = p + 512 + size_t(kMaxPart) * sizeof(double);
-  ctx->s.st_a = reinterpret_cast<uint64_t*>(q);
-  ctx->s.st_b = reinterpret_cast<uint64_t*>(q + st_bytes);
-  ctx->s.st_out = reinterpret_cast<uint64_t*>(q + 2 * st_bytes);
-  ctx->d_res = reinterpret_cast<hoszp_result*>(q + 3 * st_bytes);
+  uint8_t* q = static_cast<uint8_t*>(ctx->d_mem);
+  ctx->s.ctrl = reinterpret_cast<uint32_t*>(q);
+  q += ctrl_b;
+  ctx->s.acc = reinterpret_cast<uint64_t*>(q);
+  q += acc_b;
+  ctx->s.part = reinterpret_cast<double*>(q);
+  q += part_b;
+  ctx->s.st_out = reinterpret_cast<uint64_t*>(q);
+  q += st_b;
+  for (int k = 0; k < 2; ++k) {
+    ctx->s.idx[k].chunk_off = reinterpret_cast<uint64_t*>(q);
+    ctx->s.idx[k].tile_words = reinterpret_cast<uint32_t*>(q + off_b);
+    ctx->s.idx[k].chunk_words = reinterpret_cast<uint32_t*>(q + off_b + tw_b);
+    q += idx_b;
+  }
+  ctx->d_res = reinterpret_cast<hoszp_result*>(q);
   ctx->s.max_tiles = kMaxTiles;
   ctx->s.max_part = kMaxPart;
   ctx->epoch = 0;
@@ -239,9 +260,7 @@ int hoszp_compress_async(hoszp_ctx* ctx, const float* d_x, uint64_t n, double eb
   uint32_t epoch;
   int rc = next_epoch(ctx, st, &epoch);
   if (rc) return rc;
-  rc = device_status(hz::launch_init(ctx->s, d_res, st));
-  if (rc) return rc;
-  return device_status(hz::launch_compress(ctx->s, ctx->grids, d_x, g, inv2e,
+  return launched(ctx, d_res, st, hz::launch_compress(ctx->s, ctx->grids, d_x, g, inv2e,
                                            static_cast<uint8_t*>(d_out), epoch, d_res, st));
 }
 
@@ -265,9 +284,7 @@ int hoszp_decompress_async(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, floa
   uint32_t epoch;
   int rc = next_epoch(ctx, st, &epoch);
   if (rc) return rc;
-  rc = device_status(hz::launch_init(ctx->s, d_res, st));
-  if (rc) return rc;
-  return device_status(hz::launch_decompress(ctx->s, ctx->grids,
+  return launched(ctx, d_res, st, hz::launch_decompress(ctx->s, ctx->grids,
                                              static_cast<const uint8_t*>(d_c), c_bytes, d_x,
                                              n_cap, epoch, d_res, st));
 }
@@ -288,9 +305,7 @@ int hoszp_negate_async(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, void* d_
   DeviceScope scope(ctx->device);
   if (!scope.ok()) return HOSZP_ERR_DEVICE;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  int rc = device_status(hz::launch_init(ctx->s, d_res, st));
-  if (rc) return rc;
-  return device_status(hz::launch_negate(ctx->s, ctx->grids, static_cast<const uint8_t*>(d_c),
+  return launched(ctx, d_res, st, hz::launch_negate(ctx->s, ctx->grids, static_cast<const uint8_t*>(d_c),
                                          c_bytes, static_cast<uint8_t*>(d_out), out_cap, d_res,
                                          st));
 }
@@ -318,9 +333,7 @@ int hoszp_add_async(hoszp_ctx* ctx, const void* d_a, size_t a_bytes, const void*
   uint32_t epoch;
   int rc = next_epoch(ctx, st, &epoch);
   if (rc) return rc;
-  rc = device_status(hz::launch_init(ctx->s, d_res, st));
-  if (rc) return rc;
-  return device_status(hz::launch_add(ctx->s, ctx->grids, static_cast<const uint8_t*>(d_a),
+  return launched(ctx, d_res, st, hz::launch_add(ctx->s, ctx->grids, static_cast<const uint8_t*>(d_a),
                                       a_bytes, static_cast<const uint8_t*>(d_b), b_bytes,
                                       static_cast<uint8_t*>(d_out), out_cap, epoch, d_res, st));
 }
@@ -346,9 +359,7 @@ int hoszp_mul_async(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, double s, v
   uint32_t epoch;
   int rc = next_epoch(ctx, st, &epoch);
   if (rc) return rc;
-  rc = device_status(hz::launch_init(ctx->s, d_res, st));
-  if (rc) return rc;
-  return device_status(hz::launch_mul(ctx->s, ctx->grids, static_cast<const uint8_t*>(d_c),
+  return launched(ctx, d_res, st, hz::launch_mul(ctx->s, ctx->grids, static_cast<const uint8_t*>(d_c),
                                       c_bytes, mul_split(s), static_cast<uint8_t*>(d_out),
                                       out_cap, epoch, d_res, st));
 }
@@ -373,9 +384,7 @@ static int reduce_async(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, bool va
   uint32_t epoch;
   int rc = next_epoch(ctx, st, &epoch);
   if (rc) return rc;
-  rc = device_status(hz::launch_init(ctx->s, d_res, st));
-  if (rc) return rc;
-  return device_status(hz::launch_reduce(ctx->s, ctx->grids, static_cast<const uint8_t*>(d_c),
+  return launched(ctx, d_res, st, hz::launch_reduce(ctx->s, ctx->grids, static_cast<const uint8_t*>(d_c),
                                          c_bytes, variance, epoch, d_res, st));
 }
 
@@ -443,9 +452,7 @@ static int f32_reduce(hoszp_ctx* ctx, const float* x, uint64_t n, bool variance,
   DeviceScope scope(ctx->device);
   if (!scope.ok()) return HOSZP_ERR_DEVICE;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  int rc = device_status(hz::launch_init(ctx->s, d_res, st));
-  if (rc) return rc;
-  return device_status(hz::launch_f32_reduce(ctx->s, ctx->grids, x, n, variance, d_res, st));
+  return launched(ctx, d_res, st, hz::launch_f32_reduce(ctx->s, ctx->grids, x, n, variance, d_res, st));
 }
 
 int hoszp_f32_mean_async(hoszp_ctx* ctx, const float* d_x, uint64_t n, hoszp_result* d_res,

@@ -68,15 +68,28 @@ __host__ __device__ inline uint64_t bound_bytes(uint64_t n, uint32_t L) {
   return g.off_p + 4 * uint64_t(L) * g.nb;
 }
 
+// Tiles are grouped in chunks of kChunkTiles for the width pre-pass: the
+// pre-pass stores every tile's payload word count and the exclusive prefix
+// of every chunk; a tile's offset is its chunk's prefix plus at most 63 tile
+// counts (one wave-wide load).
+constexpr int kChunkTiles = 64;
+
+// Per-stream results of the width pre-pass.
+struct TileIndex {
+  uint32_t* tile_words;   // payload words of every tile
+  uint32_t* chunk_words;  // payload words of every chunk
+  uint64_t* chunk_off;    // exclusive prefix of chunk_words
+};
+
 // Device scratch owned by a context.
 struct Scratch {
-  uint32_t* ctrl;       // [0] tile ticket, [1] finished-tile counter
+  uint32_t* ctrl;       // [0] tile ticket, [1] finished-workgroup counter,
+                        // [2], [3] width pre-pass counters (stream A, B)
   uint64_t* acc;        // [0] S, [1] Q lo, [2] Q hi, [3] width sum
   double* part;         // per-workgroup partials of the float32 reductions
-  uint64_t* st_a;       // look-back status words (input A / only input)
-  uint64_t* st_b;       // look-back status words (input B)
-  uint64_t* st_out;     // look-back status words (output stream)
-  uint32_t max_tiles;   // capacity of each status array
+  uint64_t* st_out;     // look-back status words of an output stream
+  TileIndex idx[2];     // width pre-pass of input stream A and B
+  uint32_t max_tiles;   // capacity of the per-tile arrays
   uint32_t max_part;    // capacity of `part`
 };
 
@@ -89,11 +102,13 @@ struct MulScalar {
 
 // Occupancy-derived persistent grid sizes, filled at context creation.
 struct Grids {
-  int compress, decode, add, mul, negate, f32;
+  int compress, decode, add, mul, negate, widths, f32;
 };
 
 // ---- launchers (kernels.hip) ----------------------------------------------
-hipError_t launch_init(const Scratch& s, hoszp_result* res, hipStream_t st);
+// Clears the context counters and a result record; only needed after a
+// failed launch left an operation half-enqueued.
+hipError_t launch_reset(const Scratch& s, hoszp_result* res, hipStream_t st);
 hipError_t launch_compress(const Scratch& s, const Grids& gr, const float* x, const Layout& g,
                            double inv2e, uint8_t* out, uint32_t epoch, hoszp_result* res,
                            hipStream_t st);

@@ -4,15 +4,19 @@
 // into L/32 segments of 32 slots.  One thread owns one segment, a workgroup of
 // 256 threads owns a tile of 256 segments (8192 slots).  A segment of a block
 // of width w owns exactly w payload words (32 slots x w bits), so payload
-// offsets are a prefix sum of per-segment widths: within a tile it is a
-// workgroup scan, across tiles a single-pass decoupled look-back on per-tile
-// word counts (status words in the context scratch).  Tiles are taken from an
-// atomic ticket so a tile only ever waits on tiles already owned by running
-// workgroups; workgroups are persistent and loop until the tickets run out.
-//
+// offsets are prefix sums of per-segment widths:
+//   - decoders get them from a width pre-pass (k_widths) that reads only the
+//     width section and stores per-tile word counts and per-chunk prefixes;
+//   - encoders (compress, add, mul) produce them with a single-pass decoupled
+//     look-back over per-tile word counts, with tiles taken from an atomic
+//     ticket so a tile only waits on tiles owned by running workgroups.
 // Payload words are staged in LDS as big-endian values (one byte swap per
 // word), so a w-bit field at bit p of a segment is one funnel shift
 // (v_alignbit) of two neighbouring LDS words.
+//
+// Every operation ends in one kernel whose last workgroup to finish writes
+// the caller's result record and returns the context's counters to zero, so
+// an operation needs no separate initialisation launch.
 
 #include "hoszp_internal.h"
 
@@ -22,8 +26,12 @@ namespace {
 constexpr double kBinMaxD = 2147483647.0;
 constexpr uint64_t kLbAgg = 1, kLbInc = 2;
 constexpr uint64_t kLbValMask = (uint64_t(1) << 34) - 1;
+constexpr uint32_t kNone = 0xffffffffu;
 
 enum { kMean = 0, kVariance = 1, kDecompress = 2 };
+// context counters (Scratch::ctrl) and accumulators (Scratch::acc)
+enum { C_TICKET = 0, C_DONE = 1, C_WIDTHS = 2 /* 2, 3 */, C_STATUS = 4 };
+enum { A_S = 0, A_QLO = 1, A_QHI = 2, A_WSUM = 3, A_OUT = 4 };
 
 // ------------------------------------------------------------------ helpers
 
@@ -31,22 +39,75 @@ __device__ __forceinline__ uint32_t bswap32(uint32_t v) { return __builtin_bswap
 __device__ __forceinline__ uint32_t bitlen32(uint32_t v) { return v ? 32u - __clz(int(v)) : 0u; }
 
 // Values every lane holds identically, moved to scalar registers so that
-// branches on them (notably persistent-loop exits next to barriers) are
-// compiled as uniform branches.
+// branches on them (loop exits next to barriers in particular) compile to
+// uniform branches.
 __device__ __forceinline__ uint32_t uni32(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 __device__ __forceinline__ uint64_t uni64(uint64_t v) {
   return (uint64_t(uni32(uint32_t(v >> 32))) << 32) | uni32(uint32_t(v));
 }
 
-__device__ __forceinline__ void latch(hoszp_result* res, uint32_t bits) {
-  if (bits) atomicOr(&res->status, bits);
+__device__ __forceinline__ void latch(const Scratch& s, uint32_t bits) {
+  if (bits) atomicOr(&s.ctrl[C_STATUS], bits);
 }
 
-__device__ __forceinline__ uint64_t ld_acq(const uint64_t* p) {
+__device__ __forceinline__ uint64_t ld_dev(const uint64_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void st_rel(uint64_t* p, uint64_t v) {
+__device__ __forceinline__ uint32_t ld_dev32(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev(uint64_t* p, uint64_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev32(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint32_t wave_min(uint32_t v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v = min(v, uint32_t(__shfl_xor(v, d, 64)));
+  return v;
+}
+__device__ __forceinline__ uint64_t wave_sum(uint64_t v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+__device__ __forceinline__ uint32_t wave_sum32(uint32_t v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
+// Count this workgroup as finished on `counter`.  True (uniform) in the last
+// workgroup to finish.  Everything a last workgroup reads from the others
+// travels through device-scope atomics (performed at the device coherence
+// point, not in an XCD's L2), and each workgroup waits for its own memory
+// operations to complete before counting itself, so no cache write-back or
+// invalidation is needed.  Contains barriers: call from uniform control flow.
+__device__ bool finish_arrive(uint32_t* counter, uint32_t* s_flag) {
+  __builtin_amdgcn_s_waitcnt(0);  // this wave's atomics and stores have completed
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t old =
+        __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    *s_flag = old == gridDim.x - 1 ? 1u : 0u;
+  }
+  __syncthreads();
+  return uni32(*s_flag) != 0;
+}
+
+// Last workgroup of an operation: fill the caller's record and return the
+// context's counters and accumulators to zero for the next operation.
+__device__ void publish(const Scratch& s, hoszp_result* res, uint64_t out_bytes, double value) {
+  if (threadIdx.x != 0) return;
+  res->status = ld_dev32(&s.ctrl[C_STATUS]);
+  res->out_bytes = out_bytes;
+  res->value = value;
+  s.ctrl[C_TICKET] = 0;
+  s.ctrl[C_DONE] = 0;
+  s.ctrl[C_STATUS] = 0;
+  for (int k = 0; k < 8; ++k) s.acc[k] = 0;
 }
 
 // Validate a stream header and derive its section placement.
@@ -105,55 +166,154 @@ __device__ uint32_t wg_scan(uint32_t v, uint32_t& total, uint32_t* tmp) {
     all += t;
   }
   __syncthreads();
+  total = uni32(all);
+  return before + x - v;
+}
+
+__device__ uint64_t wg_scan64(uint64_t v, uint64_t& total, uint64_t* tmp) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint64_t x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint64_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) tmp[wave] = x;
+  __syncthreads();
+  uint64_t before = 0, all = 0;
+#pragma unroll
+  for (int w = 0; w < kThreads / 64; ++w) {
+    const uint64_t t = tmp[w];
+    before += (w < wave) ? t : 0u;
+    all += t;
+  }
+  __syncthreads();
   total = all;
   return before + x - v;
 }
+
+// ------------------------------------------------------------ look-back scan
 
 __device__ __forceinline__ uint64_t lb_word(uint32_t epoch, uint64_t flag, uint64_t v) {
   return (uint64_t(epoch) << 36) | (flag << 34) | (v & kLbValMask);
 }
 
+struct LbShared {
+  uint32_t first_inc[kThreads / 64];
+  uint32_t first_wait[kThreads / 64];
+  uint64_t part[kThreads / 64];
+  uint64_t near_sum;
+  uint32_t near_found;
+};
+
 // Decoupled look-back: exclusive prefix over tiles of the per-tile `agg`.
-// Executed by all 64 lanes of one wave; every lane gets the result.  The
-// tile's aggregate is published first, so a waiting tile never blocks the
-// ones before it; each window of 64 predecessors is read in parallel.
-__device__ uint64_t lookback(uint64_t* st, uint64_t tile, uint64_t agg, uint32_t epoch) {
-  const int lane = threadIdx.x & 63;
-  if (tile == 0) {
-    if (lane == 0) st_rel(&st[0], lb_word(epoch, kLbInc, agg));
-    return 0;
+// The tile publishes its aggregate first, so waiting tiles never block the
+// tiles before them.  Phase 1: wave 0 spins on the 64 nearest predecessors
+// until all have published; if none holds an inclusive prefix, phase 2 reads
+// the next older windows of kThreads tiles with the whole workgroup (one word
+// per thread), so the inclusive-prefix frontier advances hundreds of tiles
+// per device-coherent load instead of 64.  Contains barriers.
+__device__ uint64_t wg_lookback(uint64_t* st, uint64_t tile, uint64_t agg, uint32_t epoch,
+                                LbShared& sh) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) st_dev(&st[tile], lb_word(epoch, tile == 0 ? kLbInc : kLbAgg, agg));
+  if (tile == 0) return 0;
+  if (wave == 0) {
+    const int64_t idx = int64_t(tile) - 1 - lane;
+    for (;;) {
+      bool ready = true, inc = true;
+      uint64_t val = 0;
+      if (idx >= 0) {
+        const uint64_t w = ld_dev(&st[idx]);
+        const uint64_t flag = (w >> 34) & 3u;
+        ready = uint32_t(w >> 36) == epoch && flag != 0;
+        inc = ready && flag == kLbInc;
+        val = w & kLbValMask;
+      }
+      const uint64_t incm = __ballot(inc);
+      const uint64_t waitm = __ballot(!ready);
+      const uint64_t upto = incm ? (((incm & (~incm + 1)) << 1) - 1) : ~uint64_t(0);
+      if (waitm & upto) {
+        __builtin_amdgcn_s_sleep(2);
+        continue;
+      }
+      const uint64_t part = wave_sum(((upto >> lane) & 1u) ? val : 0);
+      if (lane == 0) {
+        sh.near_sum = part;
+        sh.near_found = incm ? 1u : 0u;
+      }
+      break;
+    }
   }
-  if (lane == 0) st_rel(&st[tile], lb_word(epoch, kLbAgg, agg));
-  uint64_t excl = 0;
-  int64_t base = int64_t(tile);
-  for (;;) {
-    const int64_t idx = base - 1 - lane;
-    bool ready = true, inc = true;
-    uint64_t val = 0;
-    if (idx >= 0) {
-      const uint64_t w = ld_acq(&st[idx]);
-      const uint64_t flag = (w >> 34) & 3u;
-      ready = uint32_t(w >> 36) == epoch && flag != 0;
-      inc = ready && flag == kLbInc;
-      val = w & kLbValMask;
-    }
-    const uint64_t incm = __ballot(inc);
-    const uint64_t waitm = __ballot(!ready);
-    const uint64_t upto = incm ? (((incm & (~incm + 1)) << 1) - 1) : ~uint64_t(0);
-    if (waitm & upto) {
-      __builtin_amdgcn_s_sleep(2);
-      continue;
-    }
-    uint64_t part = ((upto >> lane) & 1u) ? val : 0;
+  __syncthreads();
+  uint64_t excl = uni64(sh.near_sum);
+  const bool found = uni32(sh.near_found) != 0;
+  __syncthreads();
+  if (!found) {
+    int64_t base = int64_t(tile) - 64;  // window covers tiles base-1-tid
+    for (;;) {
+      const int64_t idx = base - 1 - tid;
+      uint32_t fi = kNone, fw = kNone;
+      uint64_t val = 0;
+      if (idx >= 0) {
+        const uint64_t w = ld_dev(&st[idx]);
+        const uint64_t flag = (w >> 34) & 3u;
+        const bool ready = uint32_t(w >> 36) == epoch && flag != 0;
+        if (!ready) fw = uint32_t(tid);
+        if (ready && flag == kLbInc) fi = uint32_t(tid);
+        val = w & kLbValMask;
+      } else {
+        fi = uint32_t(tid);  // before tile 0: an inclusive prefix of 0
+      }
+      fi = wave_min(fi);
+      fw = wave_min(fw);
+      if (lane == 0) {
+        sh.first_inc[wave] = fi;
+        sh.first_wait[wave] = fw;
+      }
+      __syncthreads();
+      fi = kNone;
+      fw = kNone;
 #pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) part += __shfl_xor(part, d, 64);
-    excl += part;
-    if (incm) break;
-    base -= 64;
+      for (int v = 0; v < kThreads / 64; ++v) {
+        fi = min(fi, sh.first_inc[v]);
+        fw = min(fw, sh.first_wait[v]);
+      }
+      fi = uni32(fi);
+      fw = uni32(fw);
+      __syncthreads();
+      if (fw < fi) {  // a tile before the nearest inclusive prefix is unpublished
+        __builtin_amdgcn_s_sleep(4);
+        continue;
+      }
+      const uint64_t part = wave_sum(uint32_t(tid) <= fi ? val : 0);
+      if (lane == 0) sh.part[wave] = part;
+      __syncthreads();
+      uint64_t total = 0;
+#pragma unroll
+      for (int v = 0; v < kThreads / 64; ++v) total += sh.part[v];
+      __syncthreads();
+      excl += uni64(total);
+      if (fi != kNone) break;
+      base -= kThreads;
+    }
   }
-  if (lane == 0) st_rel(&st[tile], lb_word(epoch, kLbInc, excl + agg));
+  if (tid == 0) st_dev(&st[tile], lb_word(epoch, kLbInc, excl + agg));
   return excl;
 }
+
+// Payload word offset of `tile` of a stream from its width pre-pass.  Run by
+// one whole wave; every lane gets the result.
+__device__ uint64_t tile_offset(const TileIndex& ix, uint64_t tile) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t chunk = tile / kChunkTiles;
+  const uint32_t r = uint32_t(tile % kChunkTiles);
+  uint64_t v = uint32_t(lane) < r ? ix.tile_words[chunk * kChunkTiles + lane] : 0u;
+  v = wave_sum(v);
+  return ix.chunk_off[chunk] + v;
+}
+
+// ------------------------------------------------------ segment primitives
 
 // Number of valid slots (0..32) of segment `sub` of block `blk`.
 __device__ __forceinline__ uint32_t seg_count(const Layout& g, uint64_t blk, uint32_t sub,
@@ -164,13 +324,15 @@ __device__ __forceinline__ uint32_t seg_count(const Layout& g, uint64_t blk, uin
   return blen > lo ? uint32_t(blen - lo < 32 ? blen - lo : 32) : 0u;
 }
 
-// w-bit field j of a segment whose words start at sp (sp[-1] and sp[w] must
-// be readable LDS words).  w in [1, 32].
+// w-bit field starting at bit p of a segment whose words start at sp (sp[-1]
+// and the word after the segment must be readable LDS words); rshift = 32 - w.
+__device__ __forceinline__ uint32_t field_at(const uint32_t* sp, uint32_t p, uint32_t rshift) {
+  const uint32_t i = (p + 31u) >> 5;
+  return __builtin_amdgcn_alignbit(sp[int(i) - 1], sp[i], 0u - p) >> rshift;
+}
+
 __device__ __forceinline__ uint32_t field(const uint32_t* sp, uint32_t j, uint32_t w) {
-  const uint32_t p = j * w;
-  const int i = int((p + 31u) >> 5);
-  const uint32_t win = __builtin_amdgcn_alignbit(sp[i - 1], sp[i], 0u - p);
-  return win >> (32u - w);
+  return field_at(sp, __umul24(j, w), 32u - w);
 }
 
 // Magnitude and sign of delta d = q - prev for two in-range bins.
@@ -198,13 +360,13 @@ __device__ __forceinline__ void pack32(uint32_t* dst, const uint32_t* mag, uint3
 // Bins of a block stay in range if |O| + (len-1)(2^w - 1) fits.
 __device__ __forceinline__ bool bins_surely_in_range(int64_t outlier, uint64_t blen, uint32_t w) {
   const uint64_t a = uint64_t(outlier < 0 ? -outlier : outlier);
-  const uint64_t step = w >= 33 ? ~uint64_t(0) : ((uint64_t(1) << w) - 1);
+  const uint64_t step = (uint64_t(1) << w) - 1;
   return a + (blen - 1) * step <= uint64_t(kBinMax);
 }
 
 // Stage payload words [base, base + words) of a stream into LDS (sp[1..]) with
 // a zero guard word on each side.  Returns false when the range leaves the
-// payload section.
+// payload section (nothing is read then).
 __device__ bool stage_payload(uint32_t* sp, const uint32_t* P, uint64_t base, uint32_t words,
                               uint64_t payload_words) {
   const bool fits = base + words <= payload_words;
@@ -250,7 +412,7 @@ __device__ double u128_to_double(uint64_t hi, uint64_t lo) {
 }
 
 // Sum over the workgroup of an int64 and an unsigned 128-bit value (hi:lo);
-// the result is valid in thread 0.
+// the result is valid in thread 0.  Contains barriers.
 __device__ void wg_sum_s_q(int64_t& s, uint64_t& qlo, uint64_t& qhi, int64_t* ts, uint64_t* tl,
                            uint64_t* th) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -285,14 +447,117 @@ __device__ void wg_sum_s_q(int64_t& s, uint64_t& qlo, uint64_t& qhi, int64_t* ts
 
 // ------------------------------------------------------------------ kernels
 
-__global__ void k_init(uint32_t* ctrl, uint64_t* acc, hoszp_result* res) {
+// Clears the context counters and a result record (error recovery only).
+__global__ void k_reset(uint32_t* ctrl, uint64_t* acc, hoszp_result* res) {
   const int t = threadIdx.x;
-  if (t < 4) ctrl[t] = 0;
+  if (t < 8) ctrl[t] = 0;
   if (t < 8) acc[t] = 0;
-  if (t == 0) {
+  if (t == 0 && res) {
     res->status = 0;
     res->out_bytes = 0;
     res->value = 0.0;
+  }
+}
+
+struct WidthParams {
+  const uint8_t* c;
+  uint64_t c_bytes;
+  TileIndex ix;
+  uint32_t* done;  // finished-workgroup counter of this pre-pass
+  Scratch s;
+};
+
+// Sum of the widths of the 4 segments 4*lane .. 4*lane+3 of a tile, each
+// segment counting its block's width; also flags widths above 32.
+__device__ __forceinline__ uint32_t widths_of_quad(const uint8_t* c, const Layout& g, uint64_t tile,
+                                                   int lane, uint32_t& bad) {
+  const uint64_t seg0 = tile * kTileSegs + 4 * uint64_t(lane);
+  if (seg0 >= g.nseg) return 0;
+  const uint8_t* W = c + g.off_w;
+  uint32_t packed, n;  // packed width bytes and their multiplicity
+  if (g.spb == 1) {
+    if (seg0 + 4 <= g.nseg) {
+      packed = *reinterpret_cast<const uint32_t*>(W + seg0);
+    } else {
+      packed = 0;
+      for (uint32_t q = 0; seg0 + q < g.nseg; ++q) packed |= uint32_t(W[seg0 + q]) << (8 * q);
+    }
+    n = 1;
+  } else if (g.spb == 2) {  // nseg is even: the quad holds one or two whole blocks
+    packed = seg0 + 4 <= g.nseg ? *reinterpret_cast<const uint16_t*>(W + seg0 / 2) : W[seg0 / 2];
+    n = 2;
+  } else {
+    packed = W[seg0 / 4];
+    n = 4;
+  }
+  // a byte b > 32 has its top bit set or carries b + 95 into bit 7
+  if ((packed | ((packed & 0x7f7f7f7fu) + 0x5f5f5f5fu)) & 0x80808080u) {
+    bad |= ST_FORMAT;
+    uint32_t ok = 0;
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t b = (packed >> (8 * q)) & 0xffu;
+      ok |= (b <= 32 ? b : 0u) << (8 * q);
+    }
+    packed = ok;
+  }
+  return n * __builtin_amdgcn_sad_u8(packed, 0u, 0u);  // sum of the 4 bytes
+}
+
+// Width pre-pass of a stream (reads only its width section): payload words of
+// every tile and the exclusive prefix of every chunk of kChunkTiles tiles, so
+// decoders locate any tile's payload without a serial scan.  Also checks
+// every width <= 32 and that the widths fill the payload exactly.
+__global__ void __launch_bounds__(kThreads) k_widths(WidthParams p) {
+  __shared__ uint32_t s_chunk[kThreads / 64];
+  __shared__ uint64_t s_tmp[kThreads / 64];
+  __shared__ uint32_t s_flag;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  Layout g;
+  const uint32_t err = read_header(p.c, p.c_bytes, g);
+  if (err) {  // decoders see the same header and stop; nothing to index
+    if (tid == 0 && blockIdx.x == 0) latch(p.s, err);
+    return;
+  }
+  const uint64_t nchunks = (g.ntiles + kChunkTiles - 1) / kChunkTiles;
+  constexpr int kTilesPerWave = kChunkTiles / (kThreads / 64);
+  uint32_t bad = 0;
+  for (uint64_t chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
+    const uint64_t t0 = chunk * kChunkTiles + uint64_t(wave) * kTilesPerWave;
+    uint32_t v[kTilesPerWave];
+#pragma unroll
+    for (int k = 0; k < kTilesPerWave; ++k) v[k] = widths_of_quad(p.c, g, t0 + k, lane, bad);
+    uint32_t csum = 0;
+#pragma unroll
+    for (int k = 0; k < kTilesPerWave; ++k) {
+      const uint32_t t = wave_sum32(v[k]);
+      if (lane == k && t0 + k < g.ntiles) p.ix.tile_words[t0 + k] = t;
+      csum += t;
+    }
+    if (lane == 0) s_chunk[wave] = csum;
+    __syncthreads();
+    if (tid == 0) {
+      uint32_t t = 0;
+      for (int v2 = 0; v2 < kThreads / 64; ++v2) t += s_chunk[v2];
+      st_dev32(&p.ix.chunk_words[chunk], t);
+    }
+    __syncthreads();
+  }
+  latch(p.s, bad);
+  if (!finish_arrive(p.done, &s_flag)) return;
+  // last workgroup: chunk counts -> chunk offsets, and the total check
+  const uint64_t per = (nchunks + kThreads - 1) / kThreads;
+  const uint64_t lo = per * tid, hi = lo + per < nchunks ? lo + per : nchunks;
+  uint64_t local = 0;
+  for (uint64_t c = lo; c < hi; ++c) local += ld_dev32(&p.ix.chunk_words[c]);
+  uint64_t total;
+  uint64_t run = wg_scan64(local, total, s_tmp);
+  for (uint64_t c = lo; c < hi; ++c) {
+    p.ix.chunk_off[c] = run;
+    run += ld_dev32(&p.ix.chunk_words[c]);
+  }
+  if (tid == 0) {
+    if (total != g.payload_bytes / 4) latch(p.s, ST_FORMAT);
+    *p.done = 0;
   }
 }
 
@@ -350,15 +615,20 @@ template <int SPB>
 __global__ void __launch_bounds__(kThreads) k_compress(CompressParams p) {
   __shared__ uint32_t s_pay[kTileWords + 2];
   __shared__ uint32_t s_tmp[kThreads / 64];
-  __shared__ uint64_t s_ticket, s_base;
+  __shared__ uint64_t s_ticket;
+  __shared__ uint32_t s_flag;
+  __shared__ LbShared s_lb;
   constexpr uint32_t L = SPB * 32;
   const int tid = threadIdx.x;
   const Layout& g = p.g;
+  uint32_t next = 0;
+  if (tid == 0) next = atomicAdd(&p.s.ctrl[C_TICKET], 1u);
   for (;;) {
-    if (tid == 0) s_ticket = atomicAdd(&p.s.ctrl[0], 1u);
+    if (tid == 0) s_ticket = next;
     __syncthreads();
     const uint64_t tile = uni64(s_ticket);
     if (tile >= g.ntiles) break;
+    if (tid == 0) next = atomicAdd(&p.s.ctrl[C_TICKET], 1u);  // next tile, fetched early
     const uint64_t seg = tile * kTileSegs + tid;
     const bool active = seg < g.nseg;
     const uint64_t blk = seg / SPB;
@@ -397,18 +667,13 @@ __global__ void __launch_bounds__(kThreads) k_compress(CompressParams p) {
 #pragma unroll
       for (int j = 0; j < 32; ++j) mag[j] = 0;
     }
-    latch(p.res, bad);
+    latch(p.s, bad);
     mx = block_max(mx, SPB);
     const uint32_t w = bitlen32(mx);
 
     uint32_t tile_words;
     const uint32_t off = wg_scan(w, tile_words, s_tmp);
-    if (tid < 64) {
-      const uint64_t base = lookback(p.s.st_out, tile, tile_words, p.epoch);
-      if (tid == 0) s_base = base;
-    }
-    __syncthreads();
-    const uint64_t base = s_base;
+    const uint64_t base = wg_lookback(p.s.st_out, tile, tile_words, p.epoch, s_lb);
     if (w > 0) pack32(&s_pay[off], mag, w);
     __syncthreads();
     uint32_t* P = reinterpret_cast<uint32_t*>(p.out + g.off_p) + base;
@@ -423,10 +688,11 @@ __global__ void __launch_bounds__(kThreads) k_compress(CompressParams p) {
     if (tid == 0 && tile == g.ntiles - 1) {
       const uint64_t payload = 4 * (base + tile_words);
       write_header(p.out, g, payload);
-      p.res->out_bytes = g.off_p + payload;
+      st_dev(&p.s.acc[A_OUT], g.off_p + payload);
     }
     __syncthreads();
   }
+  if (finish_arrive(&p.s.ctrl[C_DONE], &s_flag)) publish(p.s, p.res, ld_dev(&p.s.acc[A_OUT]), 0.0);
 }
 
 struct DecodeParams {
@@ -435,114 +701,212 @@ struct DecodeParams {
   float* x;
   uint64_t n_cap;
   Scratch s;
-  uint32_t epoch;
   hoszp_result* res;
 };
 
-// Decode a segment: in-segment prefix e_j of the deltas (e_j = bin_j - bin of
-// the slot before the segment, or - outlier for the first segment).
-// Accumulates E = sum e_j and E2 = sum e_j^2 over valid slots, keeps e_j in
-// `keep` when KEEP.  Returns the segment's delta total.
-template <bool KEEP, bool WIDE>
-__device__ __forceinline__ int64_t decode_segment(const uint32_t* sp, uint32_t sw, uint32_t w,
-                                                  uint32_t sub, uint32_t cnt, int64_t& E,
-                                                  uint64_t& E2, unsigned __int128& E2w,
-                                                  int64_t* keep) {
-  int64_t e = 0;
+// sum over the set bits b of a 32-bit word of (b + 1)
+__device__ __forceinline__ uint32_t weighted_popcount(uint32_t v) {
+  return __popc(v) + __popc(v & 0xaaaaaaaau) + 2 * __popc(v & 0xccccccccu) +
+         4 * __popc(v & 0xf0f0f0f0u) + 8 * __popc(v & 0xff00ff00u) + 16 * __popc(v & 0xffff0000u);
+}
+
+// Fast path of a full segment (32 valid slots, width 1..20) for the mean:
+// E = sum_j e_j with e_j the in-segment prefix of the deltas, which equals
+// sum_i (32 - i) d_i.  With x_i = m_i XOR (-s_i) = d_i - s_i (s_i the sign
+// bit, slot i at bit 31 - i of `signs`):
+// E = sum_i (32 - i) x_i + sum_{i: s_i} (32 - i), all in 32-bit integers.
+__device__ __forceinline__ int32_t mean_fast(const uint32_t* sp, uint32_t w, uint32_t signs,
+                                             bool first_seg) {
+  const uint32_t rs = 32u - w;
+  int32_t acc = 0;
+  uint32_t pbit = 0;
 #pragma unroll
   for (int j = 0; j < 32; ++j) {
-    int64_t d = seg_delta(sp, sw, w, j);
+    const int32_t m = int32_t(field_at(sp, pbit, rs));
+    pbit += w;
+    const int32_t x = m ^ (int32_t(signs << j) >> 31);
+    const int32_t c = j == 0 ? (first_seg ? 0 : 32) : 32 - j;
+    acc += __mul24(x, c);
+  }
+  return acc + int32_t(weighted_popcount(signs));
+}
+
+// Delta total of a full segment of width 1..20 (signs as in mean_fast).
+__device__ __forceinline__ int32_t delta_total_fast(const uint32_t* sp, uint32_t w,
+                                                    uint32_t signs, bool first_seg) {
+  const uint32_t rs = 32u - w;
+  int32_t tot = 0;
+  uint32_t pbit = 0;
+#pragma unroll
+  for (int j = 0; j < 32; ++j) {
+    const int32_t m = int32_t(field_at(sp, pbit, rs));
+    pbit += w;
+    if (!(j == 0 && first_seg)) tot += m ^ (int32_t(signs << j) >> 31);
+  }
+  return tot + int32_t(__popc(signs));
+}
+
+// Fast path of a full segment (width 1..20) for the variance: E = sum e_j
+// (int32), E2 = sum e_j^2 (int64), D = delta total.
+__device__ __forceinline__ void var_fast(const uint32_t* sp, uint32_t w, uint32_t sw,
+                                         bool first_seg, int32_t& E, int64_t& E2, int32_t& D) {
+  const uint32_t rs = 32u - w;
+  int32_t e = 0, s1 = 0;
+  int64_t s2 = 0;
+  uint32_t pbit = 0;
+#pragma unroll
+  for (int j = 0; j < 32; ++j) {
+    const int32_t m = int32_t(field_at(sp, pbit, rs));
+    pbit += w;
+    const int32_t neg = int32_t(sw << j) >> 31;
+    int32_t d = (m ^ neg) - neg;
+    if (j == 0 && first_seg) d = 0;
+    e += d;
+    s1 += e;
+    s2 += int64_t(e) * e;
+  }
+  E = s1;
+  E2 = s2;
+  D = e;
+}
+
+// Fast path of a full segment (width 1..20) for decompression: the in-segment
+// prefixes (modulo 2^32; the bins they lead to are int32).
+__device__ __forceinline__ int32_t prefix_fast(const uint32_t* sp, uint32_t w, uint32_t sw,
+                                               bool first_seg, int32_t* e_out) {
+  const uint32_t rs = 32u - w;
+  int32_t e = 0;
+  uint32_t pbit = 0;
+#pragma unroll
+  for (int j = 0; j < 32; ++j) {
+    const int32_t m = int32_t(field_at(sp, pbit, rs));
+    pbit += w;
+    const int32_t neg = int32_t(sw << j) >> 31;
+    int32_t d = (m ^ neg) - neg;
+    if (j == 0 && first_seg) d = 0;
+    e += d;
+    e_out[j] = e;
+  }
+  return e;
+}
+
+// Generic path: in-segment prefixes e_j of any segment (partial, or width up
+// to 32) with 64-bit/128-bit sums; keeps e_j when KEEP.
+template <bool KEEP>
+__device__ int64_t decode_generic(const uint32_t* sp, uint32_t sw, uint32_t w, uint32_t sub,
+                                  uint32_t cnt, int64_t& E, unsigned __int128& E2,
+                                  int64_t* keep) {
+  int64_t e = 0;
+  E = 0;
+  E2 = 0;
+#pragma unroll
+  for (int j = 0; j < 32; ++j) {
+    int64_t d = w ? seg_delta(sp, sw, w, j) : 0;
     if (j == 0 && sub == 0) d = 0;  // slot 0 of a block is the outlier
     const bool valid = uint32_t(j) < cnt;
     if (!valid) d = 0;
     e += d;
     if (valid) {
       E += e;
-      if (WIDE) {
-        const uint64_t a = uint64_t(e < 0 ? -e : e);
-        E2w += (unsigned __int128)a * a;
-      } else {
-        E2 += uint64_t(e * e);
-      }
+      const uint64_t a = uint64_t(e < 0 ? -e : e);
+      E2 += (unsigned __int128)a * a;
     }
     if (KEEP) keep[j] = e;
   }
   return e;
 }
 
+// Load the widths of a tile, scan them, and stage its payload words in LDS.
+// *s_base holds the tile's payload word offset once the scan's barriers have
+// passed.  Returns the segment's word offset in the tile.
+__device__ __forceinline__ uint32_t stage_tile(const uint8_t* c, const Layout& g, uint64_t tile,
+                                               uint32_t* s_pay, uint32_t* s_tmp,
+                                               const uint64_t* s_base, uint32_t& w,
+                                               uint32_t& tile_words, uint32_t& bad) {
+  const uint64_t seg = tile * kTileSegs + threadIdx.x;
+  w = seg < g.nseg ? c[g.off_w + seg / g.spb] : 0u;
+  if (w > 32) {
+    bad |= ST_FORMAT;
+    w = 0;
+  }
+  const uint32_t off = wg_scan(w, tile_words, s_tmp);  // its barriers publish *s_base
+  const uint64_t base = uni64(*s_base);
+  const uint32_t* P = reinterpret_cast<const uint32_t*>(c + g.off_p);
+  if (!stage_payload(s_pay, P, base, tile_words, g.payload_bytes / 4)) bad |= ST_FORMAT;
+  return off;
+}
+
 template <int MODE>
 __global__ void __launch_bounds__(kThreads) k_decode(DecodeParams p) {
   __shared__ uint32_t s_pay[kTileWords + 2];
   __shared__ uint32_t s_tmp[kThreads / 64];
-  __shared__ uint64_t s_ticket, s_base;
+  __shared__ uint64_t s_base;
+  __shared__ uint32_t s_flag;
   __shared__ int64_t s_rs[kThreads / 64];
   __shared__ uint64_t s_rl[kThreads / 64], s_rh[kThreads / 64];
   const int tid = threadIdx.x;
   Layout g;
   uint32_t err = read_header(p.c, p.c_bytes, g);
   if (!err && MODE == kDecompress && p.n_cap < g.n) err = ST_CAPACITY;
-  if (err) {
-    if (tid == 0) latch(p.res, err);
-    return;
-  }
-  const uint64_t payload_words = g.payload_bytes / 4;
-  const uint32_t* P = reinterpret_cast<const uint32_t*>(p.c + g.off_p);
+  if (tid == 0 && blockIdx.x == 0) latch(p.s, err);
+  const uint64_t ntiles = err ? 0 : g.ntiles;
   const uint32_t* S = reinterpret_cast<const uint32_t*>(p.c + g.off_s);
   const int32_t* O = reinterpret_cast<const int32_t*>(p.c + g.off_o);
   const double two_eb = 2.0 * g.eb;
-  for (;;) {
-    if (tid == 0) s_ticket = atomicAdd(&p.s.ctrl[0], 1u);
-    __syncthreads();
-    const uint64_t tile = uni64(s_ticket);
-    if (tile >= g.ntiles) break;
+  int64_t acc_s = 0;
+  uint64_t acc_ql = 0, acc_qh = 0;
+  uint32_t bad = 0;
+  for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    if (tid < 64) {
+      const uint64_t b = tile_offset(p.s.idx[0], tile);
+      if (tid == 0) s_base = b;
+    }
+    uint32_t w, tile_words;
+    const uint32_t off = stage_tile(p.c, g, tile, s_pay, s_tmp, &s_base, w, tile_words, bad);
     const uint64_t seg = tile * kTileSegs + tid;
     const bool active = seg < g.nseg;
     const uint64_t blk = seg / g.spb;
     const uint32_t sub = uint32_t(seg % g.spb);
     uint64_t blen = 0;
     const uint32_t cnt = active ? seg_count(g, blk, sub, blen) : 0u;
-    uint32_t bad = 0;
-    uint32_t w = active ? p.c[g.off_w + blk] : 0u;
-    if (w > 32) {
-      bad |= ST_FORMAT;
-      w = 0;
-    }
-    uint32_t tile_words;
-    const uint32_t off = wg_scan(w, tile_words, s_tmp);
-    if (tid < 64) {
-      const uint64_t base = lookback(p.s.st_a, tile, tile_words, p.epoch);
-      if (tid == 0) s_base = base;
-    }
-    __syncthreads();
-    const uint64_t base = s_base;
-    if (!stage_payload(s_pay, P, base, tile_words, payload_words)) bad |= ST_FORMAT;
-    if (tid == 0 && tile == g.ntiles - 1 && base + tile_words != payload_words) bad |= ST_FORMAT;
+    const int32_t outlier = active ? O[blk] : 0;
+    const uint32_t sw = (cnt > 0 && w > 0) ? bswap32(S[seg]) : 0u;
     __syncthreads();
 
-    const int32_t outlier = active ? O[blk] : 0;
-    int64_t E = 0;
+    const uint32_t* sp = &s_pay[1 + off];
+    const bool fast = cnt == 32 && w <= 20;
+    // in-segment sums: D = delta total, E = sum of prefixes, E2 = sum of squares
+    int64_t D = 0, E = 0;
     uint64_t E2 = 0;
     unsigned __int128 E2w = 0;
     int64_t keep[MODE == kDecompress ? 32 : 1];
-    int64_t D = 0;
-    const uint32_t* sp = &s_pay[1 + off];
-    if (cnt > 0 && w > 0) {
-      const uint32_t sw = bswap32(S[seg]);
-      if (MODE == kDecompress) {
-        D = decode_segment<true, false>(sp, sw, w, sub, cnt, E, E2, E2w, keep);
-      } else if (MODE == kMean || w <= 24) {
-        D = decode_segment<false, false>(sp, sw, w, sub, cnt, E, E2, E2w, keep);
-      } else {
-        D = decode_segment<false, true>(sp, sw, w, sub, cnt, E, E2, E2w, keep);
-      }
-    } else if (MODE == kDecompress) {
+    int32_t keep32[MODE == kDecompress ? 32 : 1];
+    if (fast) {
+      if (w == 0) {
+        if (MODE == kDecompress) {
 #pragma unroll
-      for (int j = 0; j < 32; ++j) keep[j] = 0;
+          for (int j = 0; j < 32; ++j) keep32[j] = 0;
+        }
+      } else if (MODE == kMean) {
+        const uint32_t signs = sub == 0 ? (sw & 0x7fffffffu) : sw;  // slot 0: the outlier
+        E = mean_fast(sp, w, signs, sub == 0);
+        if (g.spb > 1) D = delta_total_fast(sp, w, signs, sub == 0);
+      } else if (MODE == kVariance) {
+        int32_t e1, d1;
+        int64_t e2;
+        var_fast(sp, w, sw, sub == 0, e1, e2, d1);
+        E = e1;
+        E2 = uint64_t(e2);
+        D = d1;
+      } else {
+        D = prefix_fast(sp, w, sw, sub == 0, keep32);
+      }
+    } else if (cnt > 0) {
+      D = decode_generic<MODE == kDecompress>(sp, sw, w, sub, cnt, E, E2w, keep);
     }
     const int64_t carry = int64_t(outlier) + block_excl(D, g.spb);
     // every bin must be a valid int32 bin (slot 0 is the outlier itself)
     if (cnt > 0 && !bins_surely_in_range(outlier, blen, w)) {
-      const uint32_t sw = w ? bswap32(S[seg]) : 0u;
       int64_t e = 0;
       for (int j = 0; j < int(cnt); ++j) {
         if (w && !(j == 0 && sub == 0)) e += seg_delta(sp, sw, w, j);
@@ -550,20 +914,20 @@ __global__ void __launch_bounds__(kThreads) k_decode(DecodeParams p) {
         if (bin < -kBinMax || bin > kBinMax) bad |= ST_FORMAT;
       }
     }
-    latch(p.res, bad);
 
     if (MODE == kDecompress) {
       if (cnt > 0) {
         const uint64_t first = blk * g.L + uint64_t(32) * sub;
-        if (cnt == 32) {
+        if (fast) {  // bins are carry + e_j (mod 2^32), always int32 here
           float4* dst = reinterpret_cast<float4*>(p.x + first);
+          const int32_t c32 = int32_t(carry);
 #pragma unroll
           for (int k = 0; k < 8; ++k) {
             float4 t;
-            t.x = float(double(carry + keep[4 * k + 0]) * two_eb);
-            t.y = float(double(carry + keep[4 * k + 1]) * two_eb);
-            t.z = float(double(carry + keep[4 * k + 2]) * two_eb);
-            t.w = float(double(carry + keep[4 * k + 3]) * two_eb);
+            t.x = float(double(c32 + keep32[4 * k + 0]) * two_eb);
+            t.y = float(double(c32 + keep32[4 * k + 1]) * two_eb);
+            t.z = float(double(c32 + keep32[4 * k + 2]) * two_eb);
+            t.w = float(double(c32 + keep32[4 * k + 3]) * two_eb);
             dst[k] = t;
           }
         } else {
@@ -572,54 +936,56 @@ __global__ void __launch_bounds__(kThreads) k_decode(DecodeParams p) {
             if (uint32_t(j) < cnt) p.x[first + j] = float(double(carry + keep[j]) * two_eb);
         }
       }
-      __syncthreads();
-    } else {
+    } else if (cnt > 0) {
       // bins of the segment: carry + e_j over its cnt valid slots
-      int64_t s_seg = int64_t(cnt) * carry + E;
-      uint64_t qlo = 0, qhi = 0;
-      if (MODE == kVariance && cnt > 0) {
-        const __int128 c = carry;
-        __int128 q = __int128(cnt) * c * c + 2 * c * __int128(E);
-        if (w > 24) q += __int128(E2w);
-        else q += __int128(E2);
-        qlo = uint64_t(q);
-        qhi = uint64_t(q >> 64);
+      acc_s += int64_t(cnt) * carry + E;
+      if (MODE == kVariance) {
+        const __int128 cc = carry;
+        __int128 q = __int128(cnt) * cc * cc + 2 * cc * __int128(E);
+        q += fast ? __int128(E2) : __int128(E2w);
+        const uint64_t ql = uint64_t(q), qh = uint64_t(q >> 64);
+        const uint64_t nl = acc_ql + ql;
+        acc_qh += qh + (nl < acc_ql ? 1u : 0u);
+        acc_ql = nl;
       }
-      wg_sum_s_q(s_seg, qlo, qhi, s_rs, s_rl, s_rh);
-      if (tid == 0) {
-        atomicAdd(reinterpret_cast<unsigned long long*>(&p.s.acc[0]), (unsigned long long)s_seg);
-        if (MODE == kVariance) {
-          const uint64_t old =
-              atomicAdd(reinterpret_cast<unsigned long long*>(&p.s.acc[1]), (unsigned long long)qlo);
-          const uint64_t carry_out = (old + qlo < old) ? 1u : 0u;
-          atomicAdd(reinterpret_cast<unsigned long long*>(&p.s.acc[2]),
-                    (unsigned long long)(qhi + carry_out));
-        }
-        __threadfence();
-        const uint32_t done = atomicAdd(&p.s.ctrl[1], 1u);
-        if (done == g.ntiles - 1) {
-          __threadfence();
-          const int64_t S_all = int64_t(ld_acq(&p.s.acc[0]));
-          if (MODE == kMean) {
-            p.res->value = (double(S_all) / double(g.n)) * two_eb;
-          } else {
-            const uint64_t ql = ld_acq(&p.s.acc[1]), qh = ld_acq(&p.s.acc[2]);
-            // M = n Q - S^2 (exact, non-negative)
-            const uint64_t n = g.n;
-            const uint64_t nql = n * ql;
-            const uint64_t nqh = n * qh + __umul64hi(n, ql);
-            const uint64_t a = uint64_t(S_all < 0 ? -S_all : S_all);
-            const uint64_t sl = a * a, sh = __umul64hi(a, a);
-            const uint64_t ml = nql - sl;
-            const uint64_t mh = nqh - sh - (nql < sl ? 1u : 0u);
-            const double m = u128_to_double(mh, ml);
-            p.res->value = ((m / double(n)) / double(n)) * (two_eb * two_eb);
-          }
-        }
+    }
+    __syncthreads();
+  }
+  latch(p.s, bad);
+  double value = 0.0;
+  if (MODE != kDecompress) {
+    wg_sum_s_q(acc_s, acc_ql, acc_qh, s_rs, s_rl, s_rh);
+    if (tid == 0) {
+      atomicAdd(reinterpret_cast<unsigned long long*>(&p.s.acc[A_S]), (unsigned long long)acc_s);
+      if (MODE == kVariance) {
+        const uint64_t old = atomicAdd(reinterpret_cast<unsigned long long*>(&p.s.acc[A_QLO]),
+                                       (unsigned long long)acc_ql);
+        const uint64_t carry_out = (old + acc_ql < old) ? 1u : 0u;
+        atomicAdd(reinterpret_cast<unsigned long long*>(&p.s.acc[A_QHI]),
+                  (unsigned long long)(acc_qh + carry_out));
       }
-      __syncthreads();
     }
   }
+  if (!finish_arrive(&p.s.ctrl[C_DONE], &s_flag)) return;
+  if (tid == 0 && !err && MODE != kDecompress) {
+    const int64_t S_all = int64_t(ld_dev(&p.s.acc[A_S]));
+    if (MODE == kMean) {
+      value = (double(S_all) / double(g.n)) * two_eb;
+    } else {
+      const uint64_t ql = ld_dev(&p.s.acc[A_QLO]), qh = ld_dev(&p.s.acc[A_QHI]);
+      // M = n Q - S^2 (exact, non-negative)
+      const uint64_t n = g.n;
+      const uint64_t nql = n * ql;
+      const uint64_t nqh = n * qh + __umul64hi(n, ql);
+      const uint64_t a = uint64_t(S_all < 0 ? -S_all : S_all);
+      const uint64_t sl = a * a, sh = __umul64hi(a, a);
+      const uint64_t ml = nql - sl;
+      const uint64_t mh = nqh - sh - (nql < sl ? 1u : 0u);
+      const double m = u128_to_double(mh, ml);
+      value = ((m / double(n)) / double(n)) * (two_eb * two_eb);
+    }
+  }
+  publish(p.s, p.res, 0, value);
 }
 
 struct NegateParams {
@@ -631,91 +997,76 @@ struct NegateParams {
   hoszp_result* res;
 };
 
-// Negation of one 4-byte word of the stream at byte offset o.
-__device__ __forceinline__ uint32_t negate_word(const Layout& g, const uint8_t* c, uint64_t o,
-                                                uint32_t v, uint64_t& wsum, uint32_t& bad) {
-  if (o >= g.off_w && o < g.off_w + g.nb) {  // widths: copied, summed and range-checked
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      if (o + b < g.off_w + g.nb) {
-        const uint32_t w = (v >> (8 * b)) & 0xffu;
-        wsum += w;
-        if (w > 32) bad |= ST_FORMAT;
-      }
-    }
-    return v;
-  }
-  if (o >= g.off_o && o < g.off_o + 4 * g.nb) return 0u - v;  // O -> -O
-  if (o >= g.off_s && o < g.off_s + 4 * g.nseg) {              // signs of valid slots
-    const uint64_t seg = (o - g.off_s) / 4;
-    const uint64_t blk = seg / g.spb;
-    const uint32_t sub = uint32_t(seg % g.spb);
-    if (c[g.off_w + blk] == 0) return v;  // constant block: no signs
-    uint64_t blen;
-    const uint32_t cnt = seg_count(g, blk, sub, blen);
-    if (cnt == 0) return v;
-    const uint32_t be = cnt == 32 ? 0xffffffffu : ~(0xffffffffu >> cnt);
-    return v ^ bswap32(be);
-  }
-  return v;
-}
-
+// Negation streams the stream in 16-byte chunks: widths, header, padding and
+// payload are copied (widths summed and range-checked on the way), outliers
+// negated, and the sign bits of valid slots of non-constant blocks flipped.
 __global__ void __launch_bounds__(kThreads) k_negate(NegateParams p) {
-  __shared__ uint64_t s_w[kThreads / 64];
-  __shared__ uint32_t s_bad;
+  __shared__ uint32_t s_flag;
   const int tid = threadIdx.x;
   Layout g;
   uint32_t err = read_header(p.c, p.c_bytes, g);
   if (!err && p.out_cap < g.total_bytes) err = ST_CAPACITY;
-  if (err) {
-    if (tid == 0 && blockIdx.x == 0) latch(p.res, err);
-    return;
-  }
-  if (tid == 0) s_bad = 0;
-  __syncthreads();
-  const uint64_t total = g.total_bytes;  // multiple of 4
-  const uint64_t nchunk = total / 16;
+  if (tid == 0 && blockIdx.x == 0) latch(p.s, err);
+  const uint64_t nchunk = err ? 0 : (g.total_bytes + 15) / 16;  // total is a multiple of 4
   const uint64_t stride = uint64_t(gridDim.x) * kThreads;
-  const uint64_t gt = uint64_t(blockIdx.x) * kThreads + tid;
   uint64_t wsum = 0;
   uint32_t bad = 0;
   const uint4* src = reinterpret_cast<const uint4*>(p.c);
   uint4* dst = reinterpret_cast<uint4*>(p.out);
-  for (uint64_t k = gt; k < nchunk; k += stride) {
-    uint4 v = src[k];
+  const uint64_t w_end = g.off_w + g.nb, o_end = g.off_o + 4 * g.nb, s_end = g.off_s + 4 * g.nseg;
+  for (uint64_t k = uint64_t(blockIdx.x) * kThreads + tid; k < nchunk; k += stride) {
     const uint64_t o = 16 * k;
-    v.x = negate_word(g, p.c, o + 0, v.x, wsum, bad);
-    v.y = negate_word(g, p.c, o + 4, v.y, wsum, bad);
-    v.z = negate_word(g, p.c, o + 8, v.z, wsum, bad);
-    v.w = negate_word(g, p.c, o + 12, v.w, wsum, bad);
-    dst[k] = v;
-  }
-  const uint64_t tail_words = (total - 16 * nchunk) / 4;
-  for (uint64_t k = gt; k < tail_words; k += stride) {
-    const uint64_t o = 16 * nchunk + 4 * k;
-    const uint32_t v = *reinterpret_cast<const uint32_t*>(p.c + o);
-    *reinterpret_cast<uint32_t*>(p.out + o) = negate_word(g, p.c, o, v, wsum, bad);
-  }
-  if (bad) atomicOr(&s_bad, bad);
-  // width total over the grid must fill the payload
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) wsum += __shfl_xor(wsum, d, 64);
-  if ((tid & 63) == 0) s_w[tid >> 6] = wsum;
-  __syncthreads();
-  if (tid == 0) {
-    uint64_t t = 0;
-    for (int w = 0; w < kThreads / 64; ++w) t += s_w[w];
-    latch(p.res, s_bad);
-    atomicAdd(reinterpret_cast<unsigned long long*>(&p.s.acc[3]), (unsigned long long)t);
-    __threadfence();
-    const uint32_t done = atomicAdd(&p.s.ctrl[1], 1u);
-    if (done == gridDim.x - 1) {
-      __threadfence();
-      const uint64_t all = ld_acq(&p.s.acc[3]);
-      if (all * (g.L / 8) != g.payload_bytes) latch(p.res, ST_FORMAT);
-      p.res->out_bytes = total;
+    if (o + 16 > g.total_bytes) {  // last partial chunk: payload words only
+      for (uint64_t b = o; b < g.total_bytes; b += 4)
+        *reinterpret_cast<uint32_t*>(p.out + b) = *reinterpret_cast<const uint32_t*>(p.c + b);
+      continue;
     }
+    uint4 v = src[k];
+    uint32_t wd[4] = {v.x, v.y, v.z, v.w};
+    if (o >= g.off_p || o + 16 <= g.off_w) {
+      // header or payload: copy
+    } else if (o < g.off_o) {  // widths (and the padding after them)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint64_t b0 = o + 4 * q;
+        uint32_t x = wd[q];
+        if (b0 >= w_end) continue;
+        if (b0 + 4 > w_end) x &= 0xffffffffu >> (8 * (b0 + 4 - w_end));
+        if ((x | ((x & 0x7f7f7f7fu) + 0x5f5f5f5fu)) & 0x80808080u) bad |= ST_FORMAT;
+        wsum += __builtin_amdgcn_sad_u8(x, 0u, 0u);
+      }
+    } else if (o < g.off_s) {  // outliers: O -> -O
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (o + 4 * q < o_end) wd[q] = 0u - wd[q];
+    } else {  // signs
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint64_t b0 = o + 4 * q;
+        if (b0 >= s_end) continue;
+        const uint64_t seg = (b0 - g.off_s) / 4;
+        const uint64_t blk = seg / g.spb;
+        if (p.c[g.off_w + blk] == 0) continue;  // constant block: no signs
+        uint32_t cnt = 32;
+        if (blk == g.nb - 1) {
+          uint64_t blen;
+          cnt = seg_count(g, blk, uint32_t(seg % g.spb), blen);
+        }
+        if (cnt == 0) continue;
+        const uint32_t be = cnt == 32 ? 0xffffffffu : ~(0xffffffffu >> cnt);
+        wd[q] ^= bswap32(be);
+      }
+    }
+    dst[k] = make_uint4(wd[0], wd[1], wd[2], wd[3]);
   }
+  latch(p.s, bad);
+  wsum = wave_sum(wsum);
+  if ((tid & 63) == 0 && wsum)
+    atomicAdd(reinterpret_cast<unsigned long long*>(&p.s.acc[A_WSUM]), (unsigned long long)wsum);
+  if (!finish_arrive(&p.s.ctrl[C_DONE], &s_flag)) return;
+  if (tid == 0 && !err && ld_dev(&p.s.acc[A_WSUM]) * (g.L / 8) != g.payload_bytes)
+    atomicOr(&p.s.ctrl[C_STATUS], ST_FORMAT);
+  publish(p.s, p.res, err ? 0 : g.total_bytes, 0.0);
 }
 
 struct AddParams {
@@ -734,7 +1085,9 @@ __global__ void __launch_bounds__(kThreads) k_add(AddParams p) {
   __shared__ uint32_t s_a[kTileWords + 2];
   __shared__ uint32_t s_b[kTileWords + 2];
   __shared__ uint32_t s_tmp[kThreads / 64];
-  __shared__ uint64_t s_ticket, s_base_a, s_base_b, s_base_z;
+  __shared__ uint64_t s_ticket, s_base_a, s_base_b;
+  __shared__ uint32_t s_flag;
+  __shared__ LbShared s_lb;
   const int tid = threadIdx.x;
   Layout g, gb;
   uint32_t err = read_header(p.a, p.a_bytes, g);
@@ -743,83 +1096,98 @@ __global__ void __launch_bounds__(kThreads) k_add(AddParams p) {
                __double_as_longlong(g.eb) != __double_as_longlong(gb.eb)))
     err = ST_MISMATCH;
   if (!err && p.out_cap < bound_bytes(g.n, g.L)) err = ST_CAPACITY;
-  if (err) {
-    if (tid == 0) latch(p.res, err);
-    return;
-  }
-  const uint64_t pw_a = g.payload_bytes / 4, pw_b = gb.payload_bytes / 4;
-  const uint32_t* Pa = reinterpret_cast<const uint32_t*>(p.a + g.off_p);
-  const uint32_t* Pb = reinterpret_cast<const uint32_t*>(p.b + gb.off_p);
+  if (tid == 0 && blockIdx.x == 0) latch(p.s, err);
+  const uint64_t ntiles = err ? 0 : g.ntiles;
   const uint32_t* Sa = reinterpret_cast<const uint32_t*>(p.a + g.off_s);
   const uint32_t* Sb = reinterpret_cast<const uint32_t*>(p.b + gb.off_s);
   const int32_t* Oa = reinterpret_cast<const int32_t*>(p.a + g.off_o);
   const int32_t* Ob = reinterpret_cast<const int32_t*>(p.b + gb.off_o);
+  uint32_t next = 0;
+  if (tid == 0) next = atomicAdd(&p.s.ctrl[C_TICKET], 1u);
   for (;;) {
-    if (tid == 0) s_ticket = atomicAdd(&p.s.ctrl[0], 1u);
+    if (tid == 0) s_ticket = next;
     __syncthreads();
     const uint64_t tile = uni64(s_ticket);
-    if (tile >= g.ntiles) break;
+    if (tile >= ntiles) break;
+    if (tid == 0) next = atomicAdd(&p.s.ctrl[C_TICKET], 1u);
+    if (tid < 64) {
+      const uint64_t v = tile_offset(p.s.idx[0], tile);
+      if (tid == 0) s_base_a = v;
+    } else if (tid < 128) {
+      const uint64_t v = tile_offset(p.s.idx[1], tile);
+      if (tid == 64) s_base_b = v;
+    }
+    uint32_t bad = 0;
+    uint32_t wa, wb, tw_a, tw_b;
+    const uint32_t off_a = stage_tile(p.a, g, tile, s_a, s_tmp, &s_base_a, wa, tw_a, bad);
+    const uint32_t off_b = stage_tile(p.b, gb, tile, s_b, s_tmp, &s_base_b, wb, tw_b, bad);
     const uint64_t seg = tile * kTileSegs + tid;
     const bool active = seg < g.nseg;
     const uint64_t blk = seg / g.spb;
     const uint32_t sub = uint32_t(seg % g.spb);
     uint64_t blen = 0;
     const uint32_t cnt = active ? seg_count(g, blk, sub, blen) : 0u;
-    uint32_t bad = 0;
-    uint32_t wa = active ? p.a[g.off_w + blk] : 0u;
-    uint32_t wb = active ? p.b[gb.off_w + blk] : 0u;
-    if (wa > 32 || wb > 32) {
-      bad |= ST_FORMAT;
-      wa = wa > 32 ? 0 : wa;
-      wb = wb > 32 ? 0 : wb;
-    }
-    uint32_t tw_a, tw_b;
-    const uint32_t off_a = wg_scan(wa, tw_a, s_tmp);
-    const uint32_t off_b = wg_scan(wb, tw_b, s_tmp);
-    if (tid < 64) {
-      const uint64_t ba = lookback(p.s.st_a, tile, tw_a, p.epoch);
-      const uint64_t bb = lookback(p.s.st_b, tile, tw_b, p.epoch);
-      if (tid == 0) {
-        s_base_a = ba;
-        s_base_b = bb;
-      }
-    }
-    __syncthreads();
-    const uint64_t base_a = s_base_a, base_b = s_base_b;
-    if (!stage_payload(s_a, Pa, base_a, tw_a, pw_a)) bad |= ST_FORMAT;
-    if (!stage_payload(s_b, Pb, base_b, tw_b, pw_b)) bad |= ST_FORMAT;
-    if (tid == 0 && tile == g.ntiles - 1 && (base_a + tw_a != pw_a || base_b + tw_b != pw_b))
-      bad |= ST_FORMAT;
+    const int64_t oa = active ? Oa[blk] : 0, ob = active ? Ob[blk] : 0;
+    const uint32_t swa = (cnt > 0 && wa) ? bswap32(Sa[seg]) : 0u;
+    const uint32_t swb = (cnt > 0 && wb) ? bswap32(Sb[seg]) : 0u;
     __syncthreads();
 
     // O_{A+B} = O_A + O_B, P_{A+B} = P_A + P_B (signed), then re-encode
-    const int64_t oz = active ? int64_t(Oa[blk]) + int64_t(Ob[blk]) : 0;
+    const int64_t oz = oa + ob;
     uint32_t mag[32];
     uint32_t sgn = 0, mx = 0;
     int64_t D = 0;
-    const uint32_t swa = (cnt > 0 && wa) ? bswap32(Sa[seg]) : 0u;
-    const uint32_t swb = (cnt > 0 && wb) ? bswap32(Sb[seg]) : 0u;
     const uint32_t* spa = &s_a[1 + off_a];
     const uint32_t* spb = &s_b[1 + off_b];
+    if (cnt == 32 && wa <= 30 && wb <= 30) {
+      // |d_A + d_B| < 2^31: 32-bit arithmetic
+      const uint32_t ra = 32u - wa, rb = 32u - wb;
+      uint32_t pa = 0, pb = 0;
+      int32_t dsum = 0;
 #pragma unroll
-    for (int j = 0; j < 32; ++j) {
-      int64_t d = 0;
-      if (wa) d += seg_delta(spa, swa, wa, j);
-      if (wb) d += seg_delta(spb, swb, wb, j);
-      if ((j == 0 && sub == 0) || uint32_t(j) >= cnt) d = 0;
-      const bool neg = d < 0;
-      // |d| >= 2^32 only happens when some bin of the sum is out of range,
-      // which the check below reports; the truncated field stays memory-safe
-      const uint32_t m = uint32_t(neg ? -d : d);
-      mag[j] = m;
-      sgn |= uint32_t(neg) << (31 - j);
-      mx = max(mx, m);
-      D += d;
+      for (int j = 0; j < 32; ++j) {
+        int32_t d = 0;
+        if (wa) {
+          const int32_t m = int32_t(field_at(spa, pa, ra));
+          const int32_t s = int32_t(swa << j) >> 31;
+          d = (m ^ s) - s;
+        }
+        if (wb) {
+          const int32_t m = int32_t(field_at(spb, pb, rb));
+          const int32_t s = int32_t(swb << j) >> 31;
+          d += (m ^ s) - s;
+        }
+        pa += wa;
+        pb += wb;
+        if (j == 0 && sub == 0) d = 0;
+        const uint32_t neg = uint32_t(d) >> 31;
+        const uint32_t m = neg ? 0u - uint32_t(d) : uint32_t(d);
+        mag[j] = m;
+        sgn |= neg << (31 - j);
+        mx = max(mx, m);
+        dsum += d;
+      }
+      D = dsum;
+    } else {
+#pragma unroll
+      for (int j = 0; j < 32; ++j) {
+        int64_t d = 0;
+        if (wa) d += seg_delta(spa, swa, wa, j);
+        if (wb) d += seg_delta(spb, swb, wb, j);
+        if ((j == 0 && sub == 0) || uint32_t(j) >= cnt) d = 0;
+        const bool neg = d < 0;
+        // |d| >= 2^32 only happens when some bin of the sum is out of range,
+        // which the check below reports; the truncated field stays memory-safe
+        const uint32_t m = uint32_t(neg ? -d : d);
+        mag[j] = m;
+        sgn |= uint32_t(neg) << (31 - j);
+        mx = max(mx, m);
+        D += d;
+      }
     }
     // every bin of the sum must stay in range
     const int64_t carry = oz + block_excl(D, g.spb);
     if (cnt > 0) {
-      const int64_t oa = Oa[blk], ob = Ob[blk];
       const uint64_t aa = uint64_t(oa < 0 ? -oa : oa), ab = uint64_t(ob < 0 ? -ob : ob);
       const uint64_t sa = (uint64_t(1) << wa) - 1, sb = (uint64_t(1) << wb) - 1;
       if (aa + ab + (blen - 1) * (sa + sb) > uint64_t(kBinMax)) {
@@ -834,17 +1202,12 @@ __global__ void __launch_bounds__(kThreads) k_add(AddParams p) {
         }
       }
     }
-    latch(p.res, bad);
+    latch(p.s, bad);
     mx = block_max(mx, g.spb);
     const uint32_t w = bitlen32(mx);
     uint32_t tw_z;
-    const uint32_t off_z = wg_scan(w, tw_z, s_tmp);
-    if (tid < 64) {
-      const uint64_t bz = lookback(p.s.st_out, tile, tw_z, p.epoch);
-      if (tid == 0) s_base_z = bz;
-    }
-    __syncthreads();  // also: every thread is done reading s_a
-    const uint64_t base_z = s_base_z;
+    const uint32_t off_z = wg_scan(w, tw_z, s_tmp);  // barriers: all threads done reading s_a
+    const uint64_t base_z = wg_lookback(p.s.st_out, tile, tw_z, p.epoch, s_lb);
     if (w > 0) pack32(&s_a[off_z], mag, w);
     __syncthreads();
     uint32_t* Pz = reinterpret_cast<uint32_t*>(p.out + g.off_p) + base_z;
@@ -859,10 +1222,11 @@ __global__ void __launch_bounds__(kThreads) k_add(AddParams p) {
     if (tid == 0 && tile == g.ntiles - 1) {
       const uint64_t payload = 4 * (base_z + tw_z);
       write_header(p.out, g, payload);
-      p.res->out_bytes = g.off_p + payload;
+      st_dev(&p.s.acc[A_OUT], g.off_p + payload);
     }
     __syncthreads();
   }
+  if (finish_arrive(&p.s.ctrl[C_DONE], &s_flag)) publish(p.s, p.res, ld_dev(&p.s.acc[A_OUT]), 0.0);
 }
 
 struct MulParams {
@@ -894,59 +1258,50 @@ __device__ __forceinline__ int32_t scaled_bin(int64_t q, const MulScalar& k, uin
 __global__ void __launch_bounds__(kThreads) k_mul(MulParams p) {
   __shared__ uint32_t s_pay[kTileWords + 2];
   __shared__ uint32_t s_tmp[kThreads / 64];
-  __shared__ uint64_t s_ticket, s_base, s_base_z;
+  __shared__ uint64_t s_ticket, s_base;
+  __shared__ uint32_t s_flag;
+  __shared__ LbShared s_lb;
   const int tid = threadIdx.x;
   Layout g;
   uint32_t err = read_header(p.c, p.c_bytes, g);
   if (!err && p.out_cap < bound_bytes(g.n, g.L)) err = ST_CAPACITY;
-  if (err) {
-    if (tid == 0) latch(p.res, err);
-    return;
-  }
-  const uint64_t payload_words = g.payload_bytes / 4;
-  const uint32_t* P = reinterpret_cast<const uint32_t*>(p.c + g.off_p);
+  if (tid == 0 && blockIdx.x == 0) latch(p.s, err);
+  const uint64_t ntiles = err ? 0 : g.ntiles;
   const uint32_t* S = reinterpret_cast<const uint32_t*>(p.c + g.off_s);
   const int32_t* O = reinterpret_cast<const int32_t*>(p.c + g.off_o);
+  uint32_t next = 0;
+  if (tid == 0) next = atomicAdd(&p.s.ctrl[C_TICKET], 1u);
   for (;;) {
-    if (tid == 0) s_ticket = atomicAdd(&p.s.ctrl[0], 1u);
+    if (tid == 0) s_ticket = next;
     __syncthreads();
     const uint64_t tile = uni64(s_ticket);
-    if (tile >= g.ntiles) break;
+    if (tile >= ntiles) break;
+    if (tid == 0) next = atomicAdd(&p.s.ctrl[C_TICKET], 1u);
+    if (tid < 64) {
+      const uint64_t v = tile_offset(p.s.idx[0], tile);
+      if (tid == 0) s_base = v;
+    }
+    uint32_t bad = 0;
+    uint32_t w, tile_words;
+    const uint32_t off = stage_tile(p.c, g, tile, s_pay, s_tmp, &s_base, w, tile_words, bad);
     const uint64_t seg = tile * kTileSegs + tid;
     const bool active = seg < g.nseg;
     const uint64_t blk = seg / g.spb;
     const uint32_t sub = uint32_t(seg % g.spb);
     uint64_t blen = 0;
     const uint32_t cnt = active ? seg_count(g, blk, sub, blen) : 0u;
-    uint32_t bad = 0;
-    uint32_t w = active ? p.c[g.off_w + blk] : 0u;
-    if (w > 32) {
-      bad |= ST_FORMAT;
-      w = 0;
-    }
-    uint32_t tile_words;
-    const uint32_t off = wg_scan(w, tile_words, s_tmp);
-    if (tid < 64) {
-      const uint64_t base = lookback(p.s.st_a, tile, tile_words, p.epoch);
-      if (tid == 0) s_base = base;
-    }
-    __syncthreads();
-    const uint64_t base = s_base;
-    if (!stage_payload(s_pay, P, base, tile_words, payload_words)) bad |= ST_FORMAT;
-    if (tid == 0 && tile == g.ntiles - 1 && base + tile_words != payload_words) bad |= ST_FORMAT;
+    const int32_t outlier = active ? O[blk] : 0;
+    const uint32_t sw = (cnt > 0 && w > 0) ? bswap32(S[seg]) : 0u;
     __syncthreads();
 
     // inverse BF + inverse LZ: bins of the segment
-    const int32_t outlier = active ? O[blk] : 0;
     int64_t e_of[32];
     int64_t D = 0;
     {
       int64_t E = 0;
-      uint64_t E2 = 0;
       unsigned __int128 E2w = 0;
-      if (cnt > 0 && w > 0) {
-        const uint32_t sw = bswap32(S[seg]);
-        D = decode_segment<true, false>(&s_pay[1 + off], sw, w, sub, cnt, E, E2, E2w, e_of);
+      if (cnt > 0) {
+        D = decode_generic<true>(&s_pay[1 + off], sw, w, sub, cnt, E, E2w, e_of);
       } else {
 #pragma unroll
         for (int j = 0; j < 32; ++j) e_of[j] = 0;
@@ -984,17 +1339,12 @@ __global__ void __launch_bounds__(kThreads) k_mul(MulParams p) {
       sgn |= uint32_t(neg) << (31 - j);
       mx = max(mx, m);
     }
-    latch(p.res, bad);
+    latch(p.s, bad);
     mx = block_max(mx, g.spb);
     const uint32_t wz = bitlen32(mx);
     uint32_t tw_z;
     const uint32_t off_z = wg_scan(wz, tw_z, s_tmp);
-    if (tid < 64) {
-      const uint64_t bz = lookback(p.s.st_out, tile, tw_z, p.epoch);
-      if (tid == 0) s_base_z = bz;
-    }
-    __syncthreads();
-    const uint64_t base_z = s_base_z;
+    const uint64_t base_z = wg_lookback(p.s.st_out, tile, tw_z, p.epoch, s_lb);
     if (wz > 0) pack32(&s_pay[off_z], mag, wz);
     __syncthreads();
     uint32_t* Pz = reinterpret_cast<uint32_t*>(p.out + g.off_p) + base_z;
@@ -1009,10 +1359,11 @@ __global__ void __launch_bounds__(kThreads) k_mul(MulParams p) {
     if (tid == 0 && tile == g.ntiles - 1) {
       const uint64_t payload = 4 * (base_z + tw_z);
       write_header(p.out, g, payload);
-      p.res->out_bytes = g.off_p + payload;
+      st_dev(&p.s.acc[A_OUT], g.off_p + payload);
     }
     __syncthreads();
   }
+  if (finish_arrive(&p.s.ctrl[C_DONE], &s_flag)) publish(p.s, p.res, ld_dev(&p.s.acc[A_OUT]), 0.0);
 }
 
 // ---------------------------------------------------- float32 workflow ops
@@ -1047,12 +1398,12 @@ __global__ void __launch_bounds__(kThreads) k_f32_map(int op, const float* x, co
 // Sum of x (pass 0) or of (x - mean)^2 (pass 1) in float64; per-workgroup
 // partials in fixed order, the last workgroup adds them up in order.
 __global__ void __launch_bounds__(kThreads) k_f32_sum(const float* x, uint64_t n, int pass,
-                                                      double* part, uint32_t* ctrl,
-                                                      hoszp_result* res) {
+                                                      Scratch s, hoszp_result* res) {
   __shared__ double s_red[kThreads];
+  __shared__ uint32_t s_flag;
   const uint64_t stride = uint64_t(gridDim.x) * kThreads;
   const uint64_t gt = uint64_t(blockIdx.x) * kThreads + threadIdx.x;
-  const double mean = pass ? part[gridDim.x] : 0.0;
+  const double mean = pass ? s.part[gridDim.x] : 0.0;
   double acc = 0.0;
   const uint64_t n4 = n / 4;
   const float4* x4 = reinterpret_cast<const float4*>(x);
@@ -1076,19 +1427,22 @@ __global__ void __launch_bounds__(kThreads) k_f32_sum(const float* x, uint64_t n
     if (threadIdx.x < h) s_red[threadIdx.x] += s_red[threadIdx.x + h];
     __syncthreads();
   }
+  if (threadIdx.x == 0)
+    __hip_atomic_store(&s.part[blockIdx.x], s_red[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (!finish_arrive(&s.ctrl[C_DONE], &s_flag)) return;
   if (threadIdx.x == 0) {
-    part[blockIdx.x] = s_red[0];
-    __threadfence();
-    const uint32_t done = atomicAdd(&ctrl[1], 1u);
-    if (done == gridDim.x - 1) {
-      __threadfence();
-      double t = 0.0;
-      for (uint32_t b = 0; b < gridDim.x; ++b)
-        t += __hip_atomic_load(&part[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const double v = t / double(n);
-      if (pass == 0) part[gridDim.x] = v;  // mean, read by pass 1
+    double t = 0.0;
+    for (uint32_t b = 0; b < gridDim.x; ++b)
+      t += __hip_atomic_load(&s.part[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const double v = t / double(n);
+    if (pass == 0) {
+      s.part[gridDim.x] = v;  // the mean, read by pass 1
+      s.ctrl[C_DONE] = 0;     // pass 1 or the next operation counts from zero
+      res->status = 0;
+      res->out_bytes = 0;
       res->value = v;
-      ctrl[1] = 0;
+    } else {
+      publish(s, res, 0, v);
     }
   }
 }
@@ -1097,8 +1451,15 @@ __global__ void __launch_bounds__(kThreads) k_f32_sum(const float* x, uint64_t n
 
 // ------------------------------------------------------------------ launchers
 
-hipError_t launch_init(const Scratch& s, hoszp_result* res, hipStream_t st) {
-  hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, st, s.ctrl, s.acc, res);
+hipError_t launch_reset(const Scratch& s, hoszp_result* res, hipStream_t st) {
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, s.ctrl, s.acc, res);
+  return hipGetLastError();
+}
+
+static hipError_t launch_widths(const Scratch& s, const Grids& gr, int which, const uint8_t* c,
+                                uint64_t c_bytes, hipStream_t st) {
+  WidthParams p{c, c_bytes, s.idx[which], s.ctrl + C_WIDTHS + which, s};
+  hipLaunchKernelGGL(k_widths, dim3(gr.widths), dim3(kThreads), 0, st, p);
   return hipGetLastError();
 }
 
@@ -1119,14 +1480,20 @@ hipError_t launch_compress(const Scratch& s, const Grids& gr, const float* x, co
 hipError_t launch_decompress(const Scratch& s, const Grids& gr, const uint8_t* c,
                              uint64_t c_bytes, float* x, uint64_t n_cap, uint32_t epoch,
                              hoszp_result* res, hipStream_t st) {
-  DecodeParams p{c, c_bytes, x, n_cap, s, epoch, res};
+  (void)epoch;
+  hipError_t e = launch_widths(s, gr, 0, c, c_bytes, st);
+  if (e != hipSuccess) return e;
+  DecodeParams p{c, c_bytes, x, n_cap, s, res};
   hipLaunchKernelGGL(k_decode<kDecompress>, dim3(gr.decode), dim3(kThreads), 0, st, p);
   return hipGetLastError();
 }
 
 hipError_t launch_reduce(const Scratch& s, const Grids& gr, const uint8_t* c, uint64_t c_bytes,
                          bool variance, uint32_t epoch, hoszp_result* res, hipStream_t st) {
-  DecodeParams p{c, c_bytes, nullptr, 0, s, epoch, res};
+  (void)epoch;
+  hipError_t e = launch_widths(s, gr, 0, c, c_bytes, st);
+  if (e != hipSuccess) return e;
+  DecodeParams p{c, c_bytes, nullptr, 0, s, res};
   if (variance)
     hipLaunchKernelGGL(k_decode<kVariance>, dim3(gr.decode), dim3(kThreads), 0, st, p);
   else
@@ -1144,6 +1511,9 @@ hipError_t launch_negate(const Scratch& s, const Grids& gr, const uint8_t* c, ui
 hipError_t launch_add(const Scratch& s, const Grids& gr, const uint8_t* a, uint64_t a_bytes,
                       const uint8_t* b, uint64_t b_bytes, uint8_t* out, uint64_t out_cap,
                       uint32_t epoch, hoszp_result* res, hipStream_t st) {
+  hipError_t e = launch_widths(s, gr, 0, a, a_bytes, st);
+  if (e == hipSuccess) e = launch_widths(s, gr, 1, b, b_bytes, st);
+  if (e != hipSuccess) return e;
   AddParams p{a, a_bytes, b, b_bytes, out, out_cap, s, epoch, res};
   hipLaunchKernelGGL(k_add, dim3(gr.add), dim3(kThreads), 0, st, p);
   return hipGetLastError();
@@ -1152,6 +1522,8 @@ hipError_t launch_add(const Scratch& s, const Grids& gr, const uint8_t* a, uint6
 hipError_t launch_mul(const Scratch& s, const Grids& gr, const uint8_t* c, uint64_t c_bytes,
                       MulScalar k, uint8_t* out, uint64_t out_cap, uint32_t epoch,
                       hoszp_result* res, hipStream_t st) {
+  hipError_t e = launch_widths(s, gr, 0, c, c_bytes, st);
+  if (e != hipSuccess) return e;
   MulParams p{c, c_bytes, out, out_cap, k, s, epoch, res};
   hipLaunchKernelGGL(k_mul, dim3(gr.mul), dim3(kThreads), 0, st, p);
   return hipGetLastError();
@@ -1166,9 +1538,8 @@ hipError_t launch_f32_unary(const Grids& gr, int op, const float* x, const float
 hipError_t launch_f32_reduce(const Scratch& s, const Grids& gr, const float* x, uint64_t n,
                              bool variance, hoszp_result* res, hipStream_t st) {
   const uint32_t grid = uint32_t(gr.f32) < s.max_part - 1 ? uint32_t(gr.f32) : s.max_part - 1;
-  hipLaunchKernelGGL(k_f32_sum, dim3(grid), dim3(kThreads), 0, st, x, n, 0, s.part, s.ctrl, res);
-  if (variance)
-    hipLaunchKernelGGL(k_f32_sum, dim3(grid), dim3(kThreads), 0, st, x, n, 1, s.part, s.ctrl, res);
+  hipLaunchKernelGGL(k_f32_sum, dim3(grid), dim3(kThreads), 0, st, x, n, 0, s, res);
+  if (variance) hipLaunchKernelGGL(k_f32_sum, dim3(grid), dim3(kThreads), 0, st, x, n, 1, s, res);
   return hipGetLastError();
 }
 
@@ -1185,6 +1556,7 @@ hipError_t query_grids(Grids& gr, int num_cus) {
   gr.add = clampg(a);
   gr.mul = clampg(m);
   gr.negate = num_cus * 8;
+  gr.widths = num_cus;
   gr.f32 = num_cus * 4;
   return hipSuccess;
 }
