@@ -205,6 +205,87 @@ int hoszp_f32_mean_async(hoszp_ctx* ctx, const float* d_x, uint64_t n, hoszp_res
 int hoszp_f32_variance_async(hoszp_ctx* ctx, const float* d_x, uint64_t n, hoszp_result* d_res,
                              void* stream);
 
+/* ---- batched compression with per-field statistics ---------------------
+ *
+ * Many fields of uneven sizes compressed in ONE persistent kernel launch,
+ * captured once in a hipGraph and replayed by hoszp_batch_launch.  The tiles
+ * of all fields form one work list; each field gets its own payload prefix
+ * scan, its own stream (byte-identical to hoszp_compress of that field with
+ * the same block size) and, from the same pass over its bins, the values
+ * hoszp_mean and hoszp_variance would return for that stream (Sec. IV-A for
+ * the stream, Sec. V-B for the reductions).
+ *
+ * An autotuner runs inside hoszp_batch_create:
+ *   - block size, for every field whose `block` is 0: each of 32, 64, 128 is
+ *     tried on the field's first min(n, 2^20) elements and the smallest
+ *     stream wins (ties go to the larger block);
+ *   - launch width, with HOSZP_BATCH_TUNE_GRID: the whole batch is run at a
+ *     few persistent grid sizes and the fastest is kept.
+ * Both run the real kernels on the caller's data, so they write the output
+ * buffers; the captured launch rewrites them. */
+
+typedef struct hoszp_field {
+  const float* d_x;  /* n float32 values, 16-byte aligned, caller-owned */
+  uint64_t n;        /* 1 <= n <= 2^32 - 1 */
+  double eb;         /* absolute error bound, finite and > 0 */
+  uint32_t block;    /* 32, 64, 128, or 0 = chosen by the autotuner */
+  uint32_t reserved; /* must be 0 */
+  void* d_out;       /* output stream, 16-byte aligned, caller-owned */
+  uint64_t out_cap;  /* >= hoszp_compress_bound(n, block); with block 0 the
+                        largest bound over the three block sizes */
+} hoszp_field;
+
+/* Per-field outcome (64 bytes), written by the GPU. */
+typedef struct hoszp_field_result {
+  uint32_t status;    /* status bit mask as in hoszp_result (NONFINITE, RANGE) */
+  uint32_t block;     /* block size the field was compressed with */
+  uint64_t out_bytes; /* stream size */
+  double mean;        /* = hoszp_mean of the stream (0 when status != 0) */
+  double variance;    /* = hoszp_variance of the stream (0 when status != 0) */
+  uint64_t reserved[4];
+} hoszp_field_result;
+
+typedef struct hoszp_batch_info {
+  uint64_t fields;
+  uint64_t total_tiles; /* work-list length (tiles of 8192 slots) */
+  uint64_t raw_bytes;   /* sum of 4 n over the fields */
+  uint64_t device_bytes;/* device memory the plan holds */
+  uint32_t grid;        /* persistent workgroups per launch */
+  uint32_t reserved;
+} hoszp_batch_info;
+
+#define HOSZP_BATCH_TUNE_GRID 1u
+
+typedef struct hoszp_batch hoszp_batch;
+
+/* Plan a batch: check every field (ARG / CAPACITY, with *bad_field set to the
+ * first offending index when bad_field is not NULL), run the autotuner on
+ * `stream`, allocate the plan's device state (about 8 bytes per 8192 input
+ * elements plus 192 bytes per field), and capture the launch.  The field
+ * table is copied; the buffers it points to must stay valid while the plan
+ * is used.  Synchronizes `stream`. */
+int hoszp_batch_create(hoszp_ctx* ctx, const hoszp_field* fields, uint64_t count,
+                       uint32_t flags, void* stream, hoszp_batch** out, uint64_t* bad_field);
+
+/* Enqueue one replay of the captured launch on `stream` (never synchronizes).
+ * Launches of one plan must not overlap in time (the plan owns one set of
+ * counters); different plans and contexts may run concurrently. */
+int hoszp_batch_launch(hoszp_batch* b, void* stream);
+
+/* Wait for `stream` and copy the `count` per-field records of the last
+ * completed launch to h_out.  Returns the code of the first failed field
+ * (HOSZP_OK if none). */
+int hoszp_batch_results(hoszp_batch* b, hoszp_field_result* h_out, void* stream);
+
+/* Device address of the per-field records (count x 64 bytes), for callers
+ * that consume them on the GPU. */
+const hoszp_field_result* hoszp_batch_device_results(const hoszp_batch* b);
+
+int hoszp_batch_info_get(const hoszp_batch* b, hoszp_batch_info* out);
+
+/* Release a plan (the caller must have synchronized its launches). */
+int hoszp_batch_destroy(hoszp_batch* b);
+
 /* Block until `stream` is idle and return the code of a result record that
  * an async call filled (also copying it to *h_out when h_out is not NULL). */
 int hoszp_result_wait(hoszp_ctx* ctx, const hoszp_result* d_res, hoszp_result* h_out, void* stream);

@@ -43,6 +43,26 @@ class Info(ctypes.Structure):
                 ("payload_bytes", ctypes.c_uint64), ("total_bytes", ctypes.c_uint64)]
 
 
+class Field(ctypes.Structure):
+    _fields_ = [("d_x", ctypes.c_void_p), ("n", ctypes.c_uint64), ("eb", ctypes.c_double),
+                ("block", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("d_out", ctypes.c_void_p), ("out_cap", ctypes.c_uint64)]
+
+
+class FieldResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_uint32), ("block", ctypes.c_uint32),
+                ("out_bytes", ctypes.c_uint64), ("mean", ctypes.c_double),
+                ("variance", ctypes.c_double), ("reserved", ctypes.c_uint64 * 4)]
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("fields", ctypes.c_uint64), ("total_tiles", ctypes.c_uint64),
+                ("raw_bytes", ctypes.c_uint64), ("device_bytes", ctypes.c_uint64),
+                ("grid", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+BATCH_TUNE_GRID = 1
+
 _LIB = None
 _VP, _SZ, _U64, _U32, _DBL, _INT = (ctypes.c_void_p, ctypes.c_size_t, ctypes.c_uint64,
                                     ctypes.c_uint32, ctypes.c_double, ctypes.c_int)
@@ -73,6 +93,13 @@ _SIGNATURES = {
     "hoszp_f32_mean_async": (_INT, [_VP, _VP, _U64, _VP, _VP]),
     "hoszp_f32_variance_async": (_INT, [_VP, _VP, _U64, _VP, _VP]),
     "hoszp_result_wait": (_INT, [_VP, _VP, ctypes.POINTER(Result), _VP]),
+    "hoszp_batch_create": (_INT, [_VP, ctypes.POINTER(Field), _U64, _U32, _VP, ctypes.POINTER(_VP),
+                                  ctypes.POINTER(_U64)]),
+    "hoszp_batch_launch": (_INT, [_VP, _VP]),
+    "hoszp_batch_results": (_INT, [_VP, ctypes.POINTER(FieldResult), _VP]),
+    "hoszp_batch_device_results": (_VP, [_VP]),
+    "hoszp_batch_info_get": (_INT, [_VP, ctypes.POINTER(BatchInfo)]),
+    "hoszp_batch_destroy": (_INT, [_VP]),
 }
 
 
@@ -351,6 +378,71 @@ def f32_variance_async(x, res, ctx=None, stream=None):
     ctx = ctx or context(x.device.index)
     _check(_lib().hoszp_f32_variance_async(ctx.handle, _ptr(x), x.numel(), _ptr(res),
                                            _stream(stream)), "f32_variance_async")
+
+
+# ---------------------------------------------------------------- batches
+
+def batch_out_cap(n: int, block: int = 0) -> int:
+    """Output capacity a batch field needs (block 0: the autotuned case)."""
+    if block:
+        return compress_bound(n, block)
+    return max(compress_bound(n, b) for b in (32, 64, 128))
+
+
+class Batch:
+    """A planned batch: every field compressed, with its mean and variance,
+    in one captured persistent launch (see hoszp_batch_create).
+
+    fields: sequence of (x, eb, block, out) with x a contiguous float32 CUDA
+    tensor, block 32/64/128 or 0 (autotuned) and out a uint8 CUDA tensor of at
+    least batch_out_cap(x.numel(), block) bytes.  The tensors must outlive the
+    plan."""
+
+    def __init__(self, fields, tune_grid=False, ctx=None, stream=None):
+        if not fields:
+            raise HoszpError(ERR_ARG, "batch_create")
+        x0 = fields[0][0]
+        self.ctx = ctx or context(x0.device.index)
+        self.count = len(fields)
+        self._keep = [(x, out) for x, _, _, out in fields]
+        table = (Field * self.count)()
+        for i, (x, eb, block, out) in enumerate(fields):
+            table[i] = Field(x.data_ptr(), x.numel(), float(eb), int(block), 0, out.data_ptr(),
+                             _nbytes(out))
+        h = _VP()
+        bad = _U64(0)
+        rc = _lib().hoszp_batch_create(self.ctx.handle, table, self.count,
+                                       BATCH_TUNE_GRID if tune_grid else 0, _stream(stream),
+                                       ctypes.byref(h), ctypes.byref(bad))
+        if rc != OK:
+            raise HoszpError(rc, f"batch_create (field {bad.value})")
+        self.handle = h
+
+    def launch(self, stream=None):
+        _check(_lib().hoszp_batch_launch(self.handle, _stream(stream)), "batch_launch")
+
+    def results(self, stream=None):
+        """Per-field dicts: code, status, block, out_bytes, mean, variance."""
+        arr = (FieldResult * self.count)()
+        _lib().hoszp_batch_results(self.handle, arr, _stream(stream))
+        return [{"code": status_code(r.status), "status": r.status, "block": r.block,
+                 "out_bytes": r.out_bytes, "mean": r.mean, "variance": r.variance} for r in arr]
+
+    def info(self) -> dict:
+        bi = BatchInfo()
+        _check(_lib().hoszp_batch_info_get(self.handle, ctypes.byref(bi)), "batch_info")
+        return {k: getattr(bi, k) for k, _ in BatchInfo._fields_ if k != "reserved"}
+
+    def close(self):
+        if getattr(self, "handle", None) and _LIB is not None:
+            _LIB.hoszp_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def result_struct_size() -> int:

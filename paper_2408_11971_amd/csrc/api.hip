@@ -23,6 +23,18 @@ struct hoszp_ctx {
   uint32_t epoch;       // look-back generation, 28 bits, never 0
 };
 
+struct hoszp_batch {
+  int device;
+  uint64_t count;
+  hz::BatchDev dev;
+  void* d_mem;
+  uint64_t device_bytes;
+  uint64_t raw_bytes;
+  int grid;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
 namespace {
 
 constexpr uint32_t kEpochMask = (1u << 28) - 1;
@@ -53,8 +65,8 @@ int next_epoch(hoszp_ctx* ctx, hipStream_t st, uint32_t* epoch) {
   uint32_t e = (ctx->epoch + 1) & kEpochMask;
   if (e == 0) {
     e = 1;
-    const size_t bytes = size_t(ctx->s.max_tiles) * sizeof(uint64_t);
-    if (hipMemsetAsync(ctx->s.st_out, 0, bytes, st) != hipSuccess) return HOSZP_ERR_DEVICE;
+    if (hz::launch_zero64(ctx->s.st_out, ctx->s.max_tiles, st) != hipSuccess)
+      return HOSZP_ERR_DEVICE;
   }
   ctx->epoch = e;
   *epoch = e;
@@ -463,6 +475,270 @@ int hoszp_f32_mean_async(hoszp_ctx* ctx, const float* d_x, uint64_t n, hoszp_res
 int hoszp_f32_variance_async(hoszp_ctx* ctx, const float* d_x, uint64_t n, hoszp_result* d_res,
                              void* stream) {
   return f32_reduce(ctx, d_x, n, true, d_res, stream);
+}
+
+// ---- batched compression ------------------------------------------------
+
+namespace {
+
+constexpr uint64_t kTuneSample = uint64_t(1) << 20;
+const uint32_t kBlocks[3] = {32, 64, 128};
+
+uint64_t field_cap_needed(const hoszp_field& f) {
+  if (f.block) return hz::bound_bytes(f.n, f.block);
+  uint64_t m = 0;
+  for (uint32_t L : kBlocks) m = hz::bound_bytes(f.n, L) > m ? hz::bound_bytes(f.n, L) : m;
+  return m;
+}
+
+int check_field(const hoszp_field& f) {
+  if (!f.d_x || !f.d_out || !aligned(f.d_x, 16) || !aligned(f.d_out, 16) || f.reserved) return HOSZP_ERR_ARG;
+  if (f.n == 0 || f.n > hz::kMaxN || !(f.eb > 0.0) || !isfinite(f.eb)) return HOSZP_ERR_ARG;
+  if (f.block && !hz::block_ok(f.block)) return HOSZP_ERR_ARG;
+  if (f.out_cap < field_cap_needed(f)) return HOSZP_ERR_CAPACITY;
+  return HOSZP_OK;
+}
+
+// Block size of every field whose block is 0: the smallest stream of the
+// field's first min(n, kTuneSample) elements over the three block sizes.
+int tune_blocks(hoszp_ctx* ctx, const hoszp_field* fields, uint64_t count, uint32_t* blocks,
+                hipStream_t st) {
+  uint64_t auto_n = 0;
+  for (uint64_t i = 0; i < count; ++i) auto_n += fields[i].block == 0;
+  for (uint64_t i = 0; i < count; ++i) blocks[i] = fields[i].block ? fields[i].block : 32;
+  if (auto_n == 0) return HOSZP_OK;
+  hoszp_result* d_r = nullptr;
+  const size_t rb = size_t(auto_n) * 3 * sizeof(hoszp_result);
+  if (hipMalloc(&d_r, rb) != hipSuccess) return HOSZP_ERR_NOMEM;
+  int rc = HOSZP_OK;
+  uint64_t k = 0;
+  for (uint64_t i = 0; i < count && rc == HOSZP_OK; ++i) {
+    const hoszp_field& f = fields[i];
+    if (f.block) continue;
+    const uint64_t m = f.n < kTuneSample ? f.n : kTuneSample;
+    for (int j = 0; j < 3 && rc == HOSZP_OK; ++j)
+      rc = hoszp_compress_async(ctx, f.d_x, m, f.eb, kBlocks[j], f.d_out, size_t(f.out_cap),
+                                d_r + 3 * k + j, st);
+    ++k;
+  }
+  hoszp_result* h_r = nullptr;
+  if (rc == HOSZP_OK && !(h_r = new (std::nothrow) hoszp_result[auto_n * 3])) rc = HOSZP_ERR_NOMEM;
+  if (rc == HOSZP_OK && (hipMemcpyAsync(h_r, d_r, rb, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                         hipStreamSynchronize(st) != hipSuccess))
+    rc = HOSZP_ERR_DEVICE;
+  if (rc == HOSZP_OK) {
+    k = 0;
+    for (uint64_t i = 0; i < count; ++i) {
+      if (fields[i].block) continue;
+      uint32_t best = 32;
+      uint64_t best_bytes = ~uint64_t(0);
+      for (int j = 0; j < 3; ++j) {
+        const hoszp_result& r = h_r[3 * k + j];
+        if (r.status == 0 && r.out_bytes <= best_bytes) best_bytes = r.out_bytes, best = kBlocks[j];
+      }
+      blocks[i] = best;  // a field that fails at every size keeps 32 and reports at launch
+      ++k;
+    }
+  }
+  delete[] h_r;
+  (void)hipFree(d_r);
+  return rc;
+}
+
+void batch_free(hoszp_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->d_mem) (void)hipFree(b->d_mem);
+  delete b;
+}
+
+// Time one launch of the batch at `grid` workgroups (milliseconds).
+int time_grid(hoszp_batch* b, int grid, hipStream_t st, float* ms) {
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return HOSZP_ERR_DEVICE;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return HOSZP_ERR_DEVICE;
+  }
+  int rc = HOSZP_OK;
+  if (hz::launch_batch(b->dev, grid, st) != hipSuccess || hipEventRecord(e0, st) != hipSuccess ||
+      hz::launch_batch(b->dev, grid, st) != hipSuccess || hipEventRecord(e1, st) != hipSuccess ||
+      hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(ms, e0, e1) != hipSuccess)
+    rc = HOSZP_ERR_DEVICE;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
+}
+
+}  // namespace
+
+int hoszp_batch_create(hoszp_ctx* ctx, const hoszp_field* fields, uint64_t count, uint32_t flags,
+                       void* stream, hoszp_batch** out, uint64_t* bad_field) {
+  if (!out) return HOSZP_ERR_ARG;
+  *out = nullptr;
+  if (!ctx || !fields || count == 0 || count > 0xffffffffull || (flags & ~HOSZP_BATCH_TUNE_GRID))
+    return HOSZP_ERR_ARG;
+  for (uint64_t i = 0; i < count; ++i) {
+    const int rc = check_field(fields[i]);
+    if (rc) {
+      if (bad_field) *bad_field = i;
+      return rc;
+    }
+  }
+  DeviceScope scope(ctx->device);
+  if (!scope.ok()) return HOSZP_ERR_DEVICE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess)
+    return HOSZP_ERR_DEVICE;
+
+  uint32_t* blocks = new (std::nothrow) uint32_t[count];
+  hz::BatchField* hf = new (std::nothrow) hz::BatchField[count];
+  if (!blocks || !hf) {
+    delete[] blocks;
+    delete[] hf;
+    return HOSZP_ERR_NOMEM;
+  }
+  int rc = tune_blocks(ctx, fields, count, blocks, st);
+  uint64_t tiles = 0, raw = 0;
+  for (uint64_t i = 0; i < count && rc == HOSZP_OK; ++i) {
+    hz::Layout g;
+    hz::place(g, fields[i].n, blocks[i], fields[i].eb);
+    hf[i] = hz::BatchField{fields[i].d_x, static_cast<uint8_t*>(fields[i].d_out), fields[i].n,
+                           fields[i].eb, 1.0 / (2.0 * fields[i].eb), tiles, blocks[i], 0};
+    tiles += g.ntiles;
+    raw += 4 * fields[i].n;
+  }
+  delete[] blocks;
+  hoszp_batch* b = rc == HOSZP_OK ? new (std::nothrow) hoszp_batch() : nullptr;
+  if (rc == HOSZP_OK && !b) rc = HOSZP_ERR_NOMEM;
+  uint32_t* tf = nullptr;
+  if (rc == HOSZP_OK) {
+    b->device = ctx->device;
+    b->count = count;
+    b->raw_bytes = raw;
+    auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+    const size_t f_b = up(count * sizeof(hz::BatchField)), tf_b = up(tiles * sizeof(uint32_t));
+    const size_t st_b = up(tiles * sizeof(uint64_t)), ctrl_b = 256;
+    const size_t acc_b = up(count * hz::kBatchAccWords * sizeof(uint64_t));
+    const size_t res_b = up(count * sizeof(hoszp_field_result));
+    b->device_bytes = f_b + tf_b + st_b + ctrl_b + acc_b + res_b;
+    if (hipMalloc(&b->d_mem, b->device_bytes) != hipSuccess) rc = HOSZP_ERR_NOMEM;
+    if (rc == HOSZP_OK) {
+      uint8_t* q = static_cast<uint8_t*>(b->d_mem);
+      b->dev.fields = reinterpret_cast<hz::BatchField*>(q);
+      b->dev.tile_field = reinterpret_cast<uint32_t*>(q + f_b);
+      b->dev.st = reinterpret_cast<uint64_t*>(q + f_b + tf_b);
+      b->dev.ctrl = reinterpret_cast<uint32_t*>(q + f_b + tf_b + st_b);
+      b->dev.facc = reinterpret_cast<uint64_t*>(q + f_b + tf_b + st_b + ctrl_b);
+      b->dev.res = reinterpret_cast<hoszp_field_result*>(q + f_b + tf_b + st_b + ctrl_b + acc_b);
+      b->dev.total_tiles = tiles;
+      tf = new (std::nothrow) uint32_t[tiles];
+      if (!tf) rc = HOSZP_ERR_NOMEM;
+    }
+    if (rc == HOSZP_OK) {
+      uint64_t t = 0;
+      for (uint64_t i = 0; i < count; ++i) {
+        hz::Layout g;
+        hz::place(g, hf[i].n, hf[i].block, hf[i].eb);
+        for (uint64_t k = 0; k < g.ntiles; ++k) tf[t++] = uint32_t(i);
+      }
+      const uint32_t epoch1 = 1;
+      if (hipMemsetAsync(b->d_mem, 0, b->device_bytes, st) != hipSuccess ||
+          hipMemcpyAsync(b->dev.fields, hf, count * sizeof(hz::BatchField), hipMemcpyHostToDevice,
+                         st) != hipSuccess ||
+          hipMemcpyAsync(const_cast<uint32_t*>(b->dev.tile_field), tf, tiles * sizeof(uint32_t),
+                         hipMemcpyHostToDevice, st) != hipSuccess ||
+          hipMemcpyAsync(b->dev.ctrl + 2, &epoch1, sizeof epoch1, hipMemcpyHostToDevice, st) !=
+              hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
+        rc = HOSZP_ERR_DEVICE;
+    }
+  }
+  delete[] tf;
+  delete[] hf;
+  // launch width: the widest persistent grid, or the fastest of a few
+  if (rc == HOSZP_OK) {
+    const int maxg = hz::batch_max_grid(cus);
+    b->grid = maxg;
+    if (flags & HOSZP_BATCH_TUNE_GRID) {
+      const int cand[4] = {cus, 2 * cus, 3 * cus, maxg};
+      float best = 0.f;
+      for (int c = 0; c < 4 && rc == HOSZP_OK; ++c) {
+        if (cand[c] > maxg || (c > 0 && cand[c] == cand[c - 1])) continue;
+        float ms = 0.f;
+        rc = time_grid(b, cand[c], st, &ms);
+        if (rc == HOSZP_OK && (best == 0.f || ms < best)) best = ms, b->grid = cand[c];
+      }
+    }
+  }
+  if (rc == HOSZP_OK) {
+    hipStream_t cap;
+    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) {
+      rc = HOSZP_ERR_DEVICE;
+    } else {
+      if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        rc = HOSZP_ERR_DEVICE;
+      } else {
+        const hipError_t le = hz::launch_batch(b->dev, b->grid, cap);
+        const hipError_t ce = hipStreamEndCapture(cap, &b->graph);
+        if (le != hipSuccess || ce != hipSuccess ||
+            hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess)
+          rc = HOSZP_ERR_DEVICE;
+      }
+      (void)hipStreamDestroy(cap);
+    }
+  }
+  if (rc != HOSZP_OK) {
+    (void)hipGetLastError();
+    if (b) batch_free(b);
+    return rc;
+  }
+  *out = b;
+  return HOSZP_OK;
+}
+
+int hoszp_batch_launch(hoszp_batch* b, void* stream) {
+  if (!b) return HOSZP_ERR_ARG;
+  DeviceScope scope(b->device);
+  if (!scope.ok()) return HOSZP_ERR_DEVICE;
+  return device_status(hipGraphLaunch(b->exec, static_cast<hipStream_t>(stream)));
+}
+
+int hoszp_batch_results(hoszp_batch* b, hoszp_field_result* h_out, void* stream) {
+  if (!b || !h_out) return HOSZP_ERR_ARG;
+  DeviceScope scope(b->device);
+  if (!scope.ok()) return HOSZP_ERR_DEVICE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (hipMemcpyAsync(h_out, b->dev.res, b->count * sizeof(hoszp_field_result),
+                     hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return HOSZP_ERR_DEVICE;
+  for (uint64_t i = 0; i < b->count; ++i)
+    if (h_out[i].status) return hoszp_status_code(h_out[i].status);
+  return HOSZP_OK;
+}
+
+const hoszp_field_result* hoszp_batch_device_results(const hoszp_batch* b) {
+  return b ? b->dev.res : nullptr;
+}
+
+int hoszp_batch_info_get(const hoszp_batch* b, hoszp_batch_info* out) {
+  if (!b || !out) return HOSZP_ERR_ARG;
+  out->fields = b->count;
+  out->total_tiles = b->dev.total_tiles;
+  out->raw_bytes = b->raw_bytes;
+  out->device_bytes = b->device_bytes;
+  out->grid = uint32_t(b->grid);
+  out->reserved = 0;
+  return HOSZP_OK;
+}
+
+int hoszp_batch_destroy(hoszp_batch* b) {
+  if (!b) return HOSZP_OK;
+  DeviceScope scope(b->device);
+  batch_free(b);
+  return HOSZP_OK;
 }
 
 }  // extern "C"

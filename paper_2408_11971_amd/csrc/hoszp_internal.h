@@ -100,6 +100,29 @@ struct MulScalar {
   int32_t big;  // 1 when |s| >= 2^52: any non-zero bin overflows
 };
 
+// One field of a batched compress, as the kernel sees it.
+struct BatchField {
+  const float* x;
+  uint8_t* out;
+  uint64_t n;
+  double eb, inv2e;
+  uint64_t tile0;   // first work-list tile of the field
+  uint32_t block;
+  uint32_t pad;
+};
+
+// Device state of a batch plan (see k_batch).
+struct BatchDev {
+  BatchField* fields;
+  uint32_t* tile_field;
+  uint64_t total_tiles;
+  uint64_t* st;
+  uint32_t* ctrl;
+  uint64_t* facc;
+  hoszp_field_result* res;
+};
+constexpr int kBatchAccWords = 8;  // accumulator words per field
+
 // Occupancy-derived persistent grid sizes, filled at context creation.
 struct Grids {
   int compress, decode, add, mul, negate, widths, f32;
@@ -129,6 +152,9 @@ hipError_t launch_f32_unary(const Grids& gr, int op, const float* x, const float
                             float* out, uint64_t n, hipStream_t st);
 hipError_t launch_f32_reduce(const Scratch& s, const Grids& gr, const float* x, uint64_t n,
                              bool variance, hoszp_result* res, hipStream_t st);
+hipError_t launch_zero64(uint64_t* p, uint64_t n, hipStream_t st);
+hipError_t launch_batch(const BatchDev& b, int grid, hipStream_t st);
+int batch_max_grid(int num_cus);
 hipError_t query_grids(Grids& gr, int num_cus);
 
 }  // namespace hz

@@ -27,6 +27,7 @@ constexpr double kBinMaxD = 2147483647.0;
 constexpr uint64_t kLbAgg = 1, kLbInc = 2;
 constexpr uint64_t kLbValMask = (uint64_t(1) << 34) - 1;
 constexpr uint32_t kNone = 0xffffffffu;
+constexpr uint32_t kEpochLimit = 1u << 28;  // look-back epochs are 28-bit, never 0
 
 enum { kMean = 0, kVariance = 1, kDecompress = 2 };
 // context counters (Scratch::ctrl) and accumulators (Scratch::acc)
@@ -85,7 +86,7 @@ __device__ __forceinline__ uint32_t wave_sum32(uint32_t v) {
 // point, not in an XCD's L2), and each workgroup waits for its own memory
 // operations to complete before counting itself, so no cache write-back or
 // invalidation is needed.  Contains barriers: call from uniform control flow.
-__device__ bool finish_arrive(uint32_t* counter, uint32_t* s_flag) {
+__device__ __forceinline__ bool finish_arrive(uint32_t* counter, uint32_t* s_flag) {
   __builtin_amdgcn_s_waitcnt(0);  // this wave's atomics and stores have completed
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -97,9 +98,22 @@ __device__ bool finish_arrive(uint32_t* counter, uint32_t* s_flag) {
   return uni32(*s_flag) != 0;
 }
 
+// finish_arrive for a counter that reaches `total` arrivals.
+__device__ __forceinline__ bool finish_arrive_n(uint32_t* counter, uint32_t total, uint32_t* s_flag) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t old =
+        __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    *s_flag = old == total - 1 ? 1u : 0u;
+  }
+  __syncthreads();
+  return uni32(*s_flag) != 0;
+}
+
 // Last workgroup of an operation: fill the caller's record and return the
 // context's counters and accumulators to zero for the next operation.
-__device__ void publish(const Scratch& s, hoszp_result* res, uint64_t out_bytes, double value) {
+__device__ __forceinline__ void publish(const Scratch& s, hoszp_result* res, uint64_t out_bytes, double value) {
   if (threadIdx.x != 0) return;
   res->status = ld_dev32(&s.ctrl[C_STATUS]);
   res->out_bytes = out_bytes;
@@ -111,7 +125,7 @@ __device__ void publish(const Scratch& s, hoszp_result* res, uint64_t out_bytes,
 }
 
 // Validate a stream header and derive its section placement.
-__device__ uint32_t read_header(const uint8_t* c, uint64_t c_bytes, Layout& g) {
+__device__ __forceinline__ uint32_t read_header(const uint8_t* c, uint64_t c_bytes, Layout& g) {
   if (c_bytes < kHeaderBytes) return ST_FORMAT;
   const uint64_t* h = reinterpret_cast<const uint64_t*>(c);
   const uint64_t h0 = uni64(h[0]), h1 = uni64(h[1]), h2 = uni64(h[2]), h3 = uni64(h[3]);
@@ -131,7 +145,7 @@ __device__ uint32_t read_header(const uint8_t* c, uint64_t c_bytes, Layout& g) {
 }
 
 // Header and zero padding of an output stream whose payload is `payload` bytes.
-__device__ void write_header(uint8_t* out, const Layout& g, uint64_t payload) {
+__device__ __forceinline__ void write_header(uint8_t* out, const Layout& g, uint64_t payload) {
   uint64_t* h = reinterpret_cast<uint64_t*>(out);
   h[0] = uint64_t(kMagic) | (uint64_t(1) << 32);
   h[1] = g.L;
@@ -148,7 +162,7 @@ __device__ void write_header(uint8_t* out, const Layout& g, uint64_t payload) {
 
 // Exclusive scan of one value per thread over the workgroup, plus the total.
 // Contains barriers: call from workgroup-uniform control flow.
-__device__ uint32_t wg_scan(uint32_t v, uint32_t& total, uint32_t* tmp) {
+__device__ __forceinline__ uint32_t wg_scan(uint32_t v, uint32_t& total, uint32_t* tmp) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t x = v;
 #pragma unroll
@@ -170,7 +184,7 @@ __device__ uint32_t wg_scan(uint32_t v, uint32_t& total, uint32_t* tmp) {
   return before + x - v;
 }
 
-__device__ uint64_t wg_scan64(uint64_t v, uint64_t& total, uint64_t* tmp) {
+__device__ __forceinline__ uint64_t wg_scan64(uint64_t v, uint64_t& total, uint64_t* tmp) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint64_t x = v;
 #pragma unroll
@@ -213,7 +227,7 @@ struct LbShared {
 // the next older windows of kThreads tiles with the whole workgroup (one word
 // per thread), so the inclusive-prefix frontier advances hundreds of tiles
 // per device-coherent load instead of 64.  Contains barriers.
-__device__ uint64_t wg_lookback(uint64_t* st, uint64_t tile, uint64_t agg, uint32_t epoch,
+__device__ __forceinline__ uint64_t wg_lookback(uint64_t* st, uint64_t tile, uint64_t agg, uint32_t epoch,
                                 LbShared& sh) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (tid == 0) st_dev(&st[tile], lb_word(epoch, tile == 0 ? kLbInc : kLbAgg, agg));
@@ -304,7 +318,7 @@ __device__ uint64_t wg_lookback(uint64_t* st, uint64_t tile, uint64_t agg, uint3
 
 // Payload word offset of `tile` of a stream from its width pre-pass.  Run by
 // one whole wave; every lane gets the result.
-__device__ uint64_t tile_offset(const TileIndex& ix, uint64_t tile) {
+__device__ __forceinline__ uint64_t tile_offset(const TileIndex& ix, uint64_t tile) {
   const int lane = threadIdx.x & 63;
   const uint64_t chunk = tile / kChunkTiles;
   const uint32_t r = uint32_t(tile % kChunkTiles);
@@ -367,7 +381,7 @@ __device__ __forceinline__ bool bins_surely_in_range(int64_t outlier, uint64_t b
 // Stage payload words [base, base + words) of a stream into LDS (sp[1..]) with
 // a zero guard word on each side.  Returns false when the range leaves the
 // payload section (nothing is read then).
-__device__ bool stage_payload(uint32_t* sp, const uint32_t* P, uint64_t base, uint32_t words,
+__device__ __forceinline__ bool stage_payload(uint32_t* sp, const uint32_t* P, uint64_t base, uint32_t words,
                               uint64_t payload_words) {
   const bool fits = base + words <= payload_words;
   if (fits)
@@ -402,7 +416,7 @@ __device__ __forceinline__ uint32_t block_max(uint32_t v, uint32_t spb) {
 }
 
 // Correctly rounded conversion of the unsigned 128-bit value hi:lo.
-__device__ double u128_to_double(uint64_t hi, uint64_t lo) {
+__device__ __forceinline__ double u128_to_double(uint64_t hi, uint64_t lo) {
   if (hi == 0) return double(lo);
   const int lz = __clzll((long long)hi);
   const uint64_t top = lz ? (hi << lz) | (lo >> (64 - lz)) : hi;
@@ -413,7 +427,7 @@ __device__ double u128_to_double(uint64_t hi, uint64_t lo) {
 
 // Sum over the workgroup of an int64 and an unsigned 128-bit value (hi:lo);
 // the result is valid in thread 0.  Contains barriers.
-__device__ void wg_sum_s_q(int64_t& s, uint64_t& qlo, uint64_t& qhi, int64_t* ts, uint64_t* tl,
+__device__ __forceinline__ void wg_sum_s_q(int64_t& s, uint64_t& qlo, uint64_t& qhi, int64_t* ts, uint64_t* tl,
                            uint64_t* th) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -457,6 +471,14 @@ __global__ void k_reset(uint32_t* ctrl, uint64_t* acc, hoszp_result* res) {
     res->out_bytes = 0;
     res->value = 0.0;
   }
+}
+
+// Zero n 64-bit words (used instead of a memset node so the enqueueing call
+// stays capturable).
+__global__ void k_zero64(uint64_t* p, uint64_t n) {
+  for (uint64_t i = uint64_t(blockIdx.x) * kThreads + threadIdx.x; i < n;
+       i += uint64_t(gridDim.x) * kThreads)
+    p[i] = 0;
 }
 
 struct WidthParams {
@@ -577,13 +599,27 @@ __device__ __forceinline__ double bin_real(float v, double eb, double inv2e) {
   return floor(shifted * inv2e);
 }
 
+// Per-thread exact sums of bins: S = sum q (int64) and Q = sum q^2 (unsigned
+// 128-bit as hi:lo).
+struct BinSums {
+  int64_t s = 0;
+  uint64_t ql = 0, qh = 0;
+  __device__ __forceinline__ void add(int32_t q) {
+    s += q;
+    const uint64_t sq = uint64_t(int64_t(q) * int64_t(q));
+    ql += sq;
+    qh += ql < sq ? 1u : 0u;
+  }
+};
+
 // Quantize 32 values, form Lorenzo deltas, split signs and magnitudes.
-// FULL: all 32 slots valid (no padding checks).
-template <bool FULL>
+// FULL: all 32 slots valid (no padding checks).  STATS: also add the valid
+// bins to `sums`.
+template <bool FULL, bool STATS>
 __device__ __forceinline__ void quantize_segment(const float* v, uint32_t cnt, bool first_seg,
                                                  int32_t prev, double eb, double inv2e,
                                                  uint32_t* mag, uint32_t& sgn, uint32_t& mx,
-                                                 int32_t& outlier, uint32_t& bad) {
+                                                 int32_t& outlier, uint32_t& bad, BinSums& sums) {
   int32_t qp = prev;
 #pragma unroll
   for (int j = 0; j < 32; ++j) {
@@ -593,6 +629,7 @@ __device__ __forceinline__ void quantize_segment(const float* v, uint32_t cnt, b
     const int32_t q = ok ? int32_t(f) : 0;
     const bool valid = FULL || uint32_t(j) < cnt;
     if (valid && !ok) bad |= isfinite(xv) ? ST_RANGE : ST_NONFINITE;
+    if (STATS && valid) sums.add(q);
     bool neg = false;
     uint32_t m = 0;
     if (j == 0 && first_seg) {
@@ -611,88 +648,232 @@ __device__ __forceinline__ void quantize_segment(const float* v, uint32_t cnt, b
   }
 }
 
-template <int SPB>
-__global__ void __launch_bounds__(kThreads) k_compress(CompressParams p) {
-  __shared__ uint32_t s_pay[kTileWords + 2];
-  __shared__ uint32_t s_tmp[kThreads / 64];
-  __shared__ uint64_t s_ticket;
-  __shared__ uint32_t s_flag;
-  __shared__ LbShared s_lb;
+// LDS of one compress workgroup.
+struct CompressShared {
+  uint32_t pay[kTileWords + 2];
+  uint32_t tmp[kThreads / 64];
+  LbShared lb;
+  int64_t rs[kThreads / 64];
+  uint64_t rl[kThreads / 64], rh[kThreads / 64];
+  uint64_t ticket;
+  uint32_t flag;
+};
+
+// Compress tile `tile` of the field x (layout g) into `out`: Sec. IV-A
+// steps 1-3 and the Fig. 3 sections.  The tile's payload offset comes from
+// the decoupled look-back over `st` (one status word per tile of this field).
+// Returns the payload words of tiles 0..tile (uniform).  Error bits go to
+// `bad`; with STATS the tile's valid bins are added to `sums`.  Contains
+// barriers.
+template <int SPB, bool STATS>
+__device__ __forceinline__ uint64_t compress_tile(const float* x, uint8_t* out, const Layout& g, double eb,
+                                  double inv2e, uint64_t tile, uint64_t* st, uint32_t epoch,
+                                  CompressShared& sh, uint32_t& bad, BinSums& sums) {
   constexpr uint32_t L = SPB * 32;
   const int tid = threadIdx.x;
-  const Layout& g = p.g;
-  uint32_t next = 0;
-  if (tid == 0) next = atomicAdd(&p.s.ctrl[C_TICKET], 1u);
-  for (;;) {
-    if (tid == 0) s_ticket = next;
-    __syncthreads();
-    const uint64_t tile = uni64(s_ticket);
-    if (tile >= g.ntiles) break;
-    if (tid == 0) next = atomicAdd(&p.s.ctrl[C_TICKET], 1u);  // next tile, fetched early
-    const uint64_t seg = tile * kTileSegs + tid;
-    const bool active = seg < g.nseg;
-    const uint64_t blk = seg / SPB;
-    const uint32_t sub = uint32_t(seg % SPB);
-    uint64_t blen = 0;
-    const uint32_t cnt = active ? seg_count(g, blk, sub, blen) : 0u;
-    const uint64_t first = blk * L + uint64_t(32) * sub;
+  const uint64_t seg = tile * kTileSegs + tid;
+  const bool active = seg < g.nseg;
+  const uint64_t blk = seg / SPB;
+  const uint32_t sub = uint32_t(seg % SPB);
+  uint64_t blen = 0;
+  const uint32_t cnt = active ? seg_count(g, blk, sub, blen) : 0u;
+  const uint64_t first = blk * L + uint64_t(32) * sub;
 
-    uint32_t mag[32];
-    uint32_t sgn = 0, mx = 0, bad = 0;
-    int32_t outlier = 0;
-    if (cnt > 0) {
-      int32_t prev = 0;
-      if (sub > 0) {  // the slot before this segment belongs to the same block
-        const double f = bin_real(p.x[first - 1], p.eb, p.inv2e);
-        prev = (f >= -kBinMaxD && f <= kBinMaxD) ? int32_t(f) : 0;
-      }
-      float v[32];
-      if (cnt == 32) {
-        const float4* src = reinterpret_cast<const float4*>(p.x + first);
+  uint32_t mag[32];
+  uint32_t sgn = 0, mx = 0;
+  int32_t outlier = 0;
+  if (cnt > 0) {
+    int32_t prev = 0;
+    if (sub > 0) {  // the slot before this segment belongs to the same block
+      const double f = bin_real(x[first - 1], eb, inv2e);
+      prev = (f >= -kBinMaxD && f <= kBinMaxD) ? int32_t(f) : 0;
+    }
+    float v[32];
+    if (cnt == 32) {
+      const float4* src = reinterpret_cast<const float4*>(x + first);
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          const float4 t = src[k];
-          v[4 * k + 0] = t.x;
-          v[4 * k + 1] = t.y;
-          v[4 * k + 2] = t.z;
-          v[4 * k + 3] = t.w;
-        }
-        quantize_segment<true>(v, cnt, sub == 0, prev, p.eb, p.inv2e, mag, sgn, mx, outlier, bad);
-      } else {
-#pragma unroll
-        for (int j = 0; j < 32; ++j) v[j] = uint32_t(j) < cnt ? p.x[first + j] : 0.0f;
-        quantize_segment<false>(v, cnt, sub == 0, prev, p.eb, p.inv2e, mag, sgn, mx, outlier, bad);
+      for (int k = 0; k < 8; ++k) {
+        const float4 t = src[k];
+        v[4 * k + 0] = t.x;
+        v[4 * k + 1] = t.y;
+        v[4 * k + 2] = t.z;
+        v[4 * k + 3] = t.w;
       }
+      quantize_segment<true, STATS>(v, cnt, sub == 0, prev, eb, inv2e, mag, sgn, mx, outlier,
+                                    bad, sums);
     } else {
 #pragma unroll
-      for (int j = 0; j < 32; ++j) mag[j] = 0;
+      for (int j = 0; j < 32; ++j) v[j] = uint32_t(j) < cnt ? x[first + j] : 0.0f;
+      quantize_segment<false, STATS>(v, cnt, sub == 0, prev, eb, inv2e, mag, sgn, mx, outlier,
+                                     bad, sums);
     }
-    latch(p.s, bad);
-    mx = block_max(mx, SPB);
-    const uint32_t w = bitlen32(mx);
-
-    uint32_t tile_words;
-    const uint32_t off = wg_scan(w, tile_words, s_tmp);
-    const uint64_t base = wg_lookback(p.s.st_out, tile, tile_words, p.epoch, s_lb);
-    if (w > 0) pack32(&s_pay[off], mag, w);
-    __syncthreads();
-    uint32_t* P = reinterpret_cast<uint32_t*>(p.out + g.off_p) + base;
-    for (uint32_t k = tid; k < tile_words; k += kThreads) P[k] = bswap32(s_pay[k]);
-    if (active) {
-      if (sub == 0) {
-        p.out[g.off_w + blk] = uint8_t(w);
-        reinterpret_cast<int32_t*>(p.out + g.off_o)[blk] = outlier;
-      }
-      reinterpret_cast<uint32_t*>(p.out + g.off_s)[seg] = bswap32(sgn);
-    }
-    if (tid == 0 && tile == g.ntiles - 1) {
-      const uint64_t payload = 4 * (base + tile_words);
-      write_header(p.out, g, payload);
-      st_dev(&p.s.acc[A_OUT], g.off_p + payload);
-    }
-    __syncthreads();
+  } else {
+#pragma unroll
+    for (int j = 0; j < 32; ++j) mag[j] = 0;
   }
-  if (finish_arrive(&p.s.ctrl[C_DONE], &s_flag)) publish(p.s, p.res, ld_dev(&p.s.acc[A_OUT]), 0.0);
+  mx = block_max(mx, SPB);
+  const uint32_t w = bitlen32(mx);
+
+  uint32_t tile_words;
+  const uint32_t off = wg_scan(w, tile_words, sh.tmp);
+  const uint64_t base = wg_lookback(st, tile, tile_words, epoch, sh.lb);
+  if (w > 0) pack32(&sh.pay[off], mag, w);
+  __syncthreads();
+  uint32_t* P = reinterpret_cast<uint32_t*>(out + g.off_p) + base;
+  for (uint32_t k = tid; k < tile_words; k += kThreads) P[k] = bswap32(sh.pay[k]);
+  if (active) {
+    if (sub == 0) {
+      out[g.off_w + blk] = uint8_t(w);
+      reinterpret_cast<int32_t*>(out + g.off_o)[blk] = outlier;
+    }
+    reinterpret_cast<uint32_t*>(out + g.off_s)[seg] = bswap32(sgn);
+  }
+  if (tid == 0 && tile == g.ntiles - 1) write_header(out, g, 4 * (base + tile_words));
+  __syncthreads();
+  return base + tile_words;
+}
+
+template <int SPB>
+__global__ void __launch_bounds__(kThreads) k_compress(CompressParams p) {
+  __shared__ CompressShared sh;
+  const int tid = threadIdx.x;
+  const Layout& g = p.g;
+  uint32_t next = 0, bad = 0;
+  BinSums none;
+  if (tid == 0) next = atomicAdd(&p.s.ctrl[C_TICKET], 1u);
+  for (;;) {
+    if (tid == 0) sh.ticket = next;
+    __syncthreads();
+    const uint64_t tile = uni64(sh.ticket);
+    if (tile >= g.ntiles) break;
+    if (tid == 0) next = atomicAdd(&p.s.ctrl[C_TICKET], 1u);  // next tile, fetched early
+    const uint64_t words = compress_tile<SPB, false>(p.x, p.out, g, p.eb, p.inv2e, tile,
+                                                     p.s.st_out, p.epoch, sh, bad, none);
+    if (tid == 0 && tile == g.ntiles - 1) st_dev(&p.s.acc[A_OUT], g.off_p + 4 * words);
+  }
+  latch(p.s, bad);
+  if (finish_arrive(&p.s.ctrl[C_DONE], &sh.flag))
+    publish(p.s, p.res, ld_dev(&p.s.acc[A_OUT]), 0.0);
+}
+
+// mean = (S / n) 2 eps and variance = ((n Q - S^2) / n / n) (2 eps)^2 from the
+// exact sums (Sec. V-B); n Q - S^2 is formed exactly in 128 bits.
+__device__ __forceinline__ void mean_variance(uint64_t n, double eb, int64_t S, uint64_t ql, uint64_t qh,
+                              double& mean, double& var) {
+  const double two_eb = 2.0 * eb;
+  mean = (double(S) / double(n)) * two_eb;
+  const uint64_t nql = n * ql;
+  const uint64_t nqh = n * qh + __umul64hi(n, ql);
+  const uint64_t a = uint64_t(S < 0 ? -S : S);
+  const uint64_t sl = a * a, sh = __umul64hi(a, a);
+  const uint64_t ml = nql - sl;
+  const uint64_t mh = nqh - sh - (nql < sl ? 1u : 0u);
+  const double m = u128_to_double(mh, ml);
+  var = ((m / double(n)) / double(n)) * (two_eb * two_eb);
+}
+
+// ------------------------------------------------------------ batched compress
+//
+// Many fields in one persistent launch.  The tiles of all fields form one
+// work list (field order, then tile order); workgroups take tiles from one
+// ticket, so within a field tiles are taken in order and each field runs its
+// own look-back over its own range of status words.  Bins are summed exactly
+// while they are in registers, so every field's mean and variance come out
+// of the same pass.  The workgroup that finishes a field's last outstanding
+// tile writes that field's result record and clears its accumulators; the
+// last workgroup of the launch clears the launch counters and advances the
+// status-word epoch, so the launch can be replayed (a hipGraph) with nothing
+// in between.
+
+enum { B_TICKET = 0, B_DONE = 1, B_EPOCH = 2 };
+enum { F_S = 0, F_QLO = 1, F_QHI = 2, F_STATUS = 3, F_OUT = 4, F_DONE = 5, F_WORDS = kBatchAccWords };
+
+struct BatchParams {
+  const BatchField* fields;
+  const uint32_t* tile_field;  // field of every work-list tile
+  uint64_t total_tiles;
+  uint64_t* st;                // status words, one per work-list tile
+  uint32_t* ctrl;              // B_* counters
+  uint64_t* facc;              // F_WORDS words per field
+  hoszp_field_result* res;     // one record per field
+};
+
+__global__ void __launch_bounds__(kThreads) k_batch(BatchParams p) {
+  __shared__ CompressShared sh;
+  const int tid = threadIdx.x;
+  const uint32_t epoch = uni32(ld_dev32(&p.ctrl[B_EPOCH]));
+  uint32_t next = 0;
+  if (tid == 0) next = atomicAdd(&p.ctrl[B_TICKET], 1u);
+  for (;;) {
+    if (tid == 0) sh.ticket = next;
+    __syncthreads();
+    const uint64_t t = uni64(sh.ticket);
+    if (t >= p.total_tiles) break;
+    if (tid == 0) next = atomicAdd(&p.ctrl[B_TICKET], 1u);
+    const uint32_t f = uni32(p.tile_field[t]);
+    const BatchField fd = p.fields[f];
+    Layout g;
+    place(g, fd.n, fd.block, fd.eb);
+    const uint64_t tile = t - fd.tile0;
+    uint32_t bad = 0;
+    BinSums sums;
+    uint64_t words = 0;
+    switch (g.spb) {
+      case 1:
+        words = compress_tile<1, true>(fd.x, fd.out, g, fd.eb, fd.inv2e, tile, p.st + fd.tile0,
+                                       epoch, sh, bad, sums);
+        break;
+      case 2:
+        words = compress_tile<2, true>(fd.x, fd.out, g, fd.eb, fd.inv2e, tile, p.st + fd.tile0,
+                                       epoch, sh, bad, sums);
+        break;
+      default:
+        words = compress_tile<4, true>(fd.x, fd.out, g, fd.eb, fd.inv2e, tile, p.st + fd.tile0,
+                                       epoch, sh, bad, sums);
+        break;
+    }
+    wg_sum_s_q(sums.s, sums.ql, sums.qh, sh.rs, sh.rl, sh.rh);
+    // error bits of the whole tile (wave OR, then one atomic per wave)
+    bad = uint32_t(__ballot(bad & ST_RANGE) ? ST_RANGE : 0u) |
+          uint32_t(__ballot(bad & ST_NONFINITE) ? ST_NONFINITE : 0u);
+    uint64_t* acc = p.facc + uint64_t(f) * F_WORDS;
+    if ((tid & 63) == 0 && bad) atomicOr(reinterpret_cast<unsigned int*>(&acc[F_STATUS]), bad);
+    if (tid == 0) {
+      atomicAdd(reinterpret_cast<unsigned long long*>(&acc[F_S]), (unsigned long long)sums.s);
+      const uint64_t old = atomicAdd(reinterpret_cast<unsigned long long*>(&acc[F_QLO]),
+                                     (unsigned long long)sums.ql);
+      const uint64_t carry = (old + sums.ql < old) ? 1u : 0u;
+      atomicAdd(reinterpret_cast<unsigned long long*>(&acc[F_QHI]),
+                (unsigned long long)(sums.qh + carry));
+      if (tile == g.ntiles - 1) st_dev(&acc[F_OUT], g.off_p + 4 * words);
+    }
+    // the field's last outstanding tile publishes its results
+    if (finish_arrive_n(reinterpret_cast<uint32_t*>(&acc[F_DONE]), uint32_t(g.ntiles), &sh.flag) &&
+        tid == 0) {
+      const uint32_t status = uint32_t(ld_dev(&acc[F_STATUS]));
+      const int64_t S = int64_t(ld_dev(&acc[F_S]));
+      const uint64_t ql = ld_dev(&acc[F_QLO]), qh = ld_dev(&acc[F_QHI]);
+      double mean = 0.0, var = 0.0;
+      if (!status) mean_variance(g.n, g.eb, S, ql, qh, mean, var);
+      hoszp_field_result* r = &p.res[f];
+      r->status = status;
+      r->block = g.L;
+      r->out_bytes = ld_dev(&acc[F_OUT]);
+      r->mean = mean;
+      r->variance = var;
+      for (int k = 0; k < F_WORDS; ++k) acc[k] = 0;
+    }
+  }
+  if (finish_arrive_n(&p.ctrl[B_DONE], gridDim.x, &sh.flag)) {
+    const bool wrap = epoch + 1 >= kEpochLimit;  // epochs wrap: clear every status word
+    if (wrap)
+      for (uint64_t k = tid; k < p.total_tiles; k += kThreads) p.st[k] = 0;
+    if (tid == 0) {
+      p.ctrl[B_TICKET] = 0;
+      p.ctrl[B_DONE] = 0;
+      p.ctrl[B_EPOCH] = wrap ? 1u : epoch + 1;
+    }
+  }
 }
 
 struct DecodeParams {
@@ -793,7 +974,7 @@ __device__ __forceinline__ int32_t prefix_fast(const uint32_t* sp, uint32_t w, u
 // Generic path: in-segment prefixes e_j of any segment (partial, or width up
 // to 32) with 64-bit/128-bit sums; keeps e_j when KEEP.
 template <bool KEEP>
-__device__ int64_t decode_generic(const uint32_t* sp, uint32_t sw, uint32_t w, uint32_t sub,
+__device__ __forceinline__ int64_t decode_generic(const uint32_t* sp, uint32_t sw, uint32_t w, uint32_t sub,
                                   uint32_t cnt, int64_t& E, unsigned __int128& E2,
                                   int64_t* keep) {
   int64_t e = 0;
@@ -1541,6 +1722,26 @@ hipError_t launch_f32_reduce(const Scratch& s, const Grids& gr, const float* x, 
   hipLaunchKernelGGL(k_f32_sum, dim3(grid), dim3(kThreads), 0, st, x, n, 0, s, res);
   if (variance) hipLaunchKernelGGL(k_f32_sum, dim3(grid), dim3(kThreads), 0, st, x, n, 1, s, res);
   return hipGetLastError();
+}
+
+hipError_t launch_zero64(uint64_t* p, uint64_t n, hipStream_t st) {
+  const uint64_t want = (n + kThreads - 1) / kThreads;
+  const uint32_t grid = uint32_t(want < 4096 ? (want ? want : 1) : 4096);
+  hipLaunchKernelGGL(k_zero64, dim3(grid), dim3(kThreads), 0, st, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch(const BatchDev& b, int grid, hipStream_t st) {
+  BatchParams p{b.fields, b.tile_field, b.total_tiles, b.st, b.ctrl, b.facc, b.res};
+  hipLaunchKernelGGL(k_batch, dim3(uint32_t(grid)), dim3(kThreads), 0, st, p);
+  return hipGetLastError();
+}
+
+int batch_max_grid(int num_cus) {
+  int occ = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch, kThreads, 0) != hipSuccess)
+    return num_cus;
+  return num_cus * (occ < 1 ? 1 : occ);
 }
 
 hipError_t query_grids(Grids& gr, int num_cus) {

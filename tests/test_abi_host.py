@@ -88,3 +88,27 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(hz, "_LIB", None)
     with pytest.raises(hz.HoszpUnavailable):
         hz.compress_bound(10, 32)
+
+
+def test_batch_structs_match_header(lib):
+    import ctypes
+    assert ctypes.sizeof(hz.Field) == 48
+    assert ctypes.sizeof(hz.FieldResult) == 64
+    assert ctypes.sizeof(hz.BatchInfo) == 40
+
+
+def test_batch_create_rejects_null_context(lib):
+    import ctypes
+    h = ctypes.c_void_p()
+    table = (hz.Field * 1)()
+    assert lib.hoszp_batch_create(None, table, 1, 0, None, ctypes.byref(h), None) == hz.ERR_ARG
+    assert lib.hoszp_batch_launch(None, None) == hz.ERR_ARG
+    assert lib.hoszp_batch_destroy(None) == hz.OK
+    assert lib.hoszp_batch_device_results(None) is None
+
+
+def test_batch_out_cap_covers_every_block(lib):
+    for n in [1, 31, 33, 1000, 8193, 1 << 20]:
+        cap = hz.batch_out_cap(n)
+        assert cap == max(ref.bound(n, L) for L in (32, 64, 128))
+        assert hz.batch_out_cap(n, 64) == ref.bound(n, 64)
