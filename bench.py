@@ -46,6 +46,10 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=1 << 24,
                     help="elements of each field the oracle is timed on (0 = skip)")
     ap.add_argument("--trad-reps", type=int, default=3)
+    ap.add_argument("--workload", choices=("grf512", "batch"), default="grf512",
+                    help="grf512: the 512^3 field ops (default); batch: 4096 uneven fields "
+                         "compressed with mean/variance in one captured launch")
+    ap.add_argument("--batch-count", type=int, default=4096)
     return ap.parse_args()
 
 
@@ -75,6 +79,8 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the library has no "
               "multi-GPU path", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch":
+        return bench_batch(args)
     import numpy as np
     import torch
 
@@ -266,6 +272,105 @@ def main():
         "ops": ops,
     }
     print(json.dumps(line), flush=True)
+
+
+def bench_batch(args):
+    """4096 fields of log-uniform size 4 KB..64 MB (seed 7), per-field relative
+    bound 1e-2/1e-3/1e-4 of the field's range, autotuned block size and grid;
+    one step = one replay of the captured batch launch (compress every field
+    and produce its mean and variance)."""
+    import numpy as np
+    import torch
+
+    import paper_2408_11971_amd as hz
+    import synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    specs = synth.batch_specs(args.batch_count, seed=7)
+    ns = [int(np.prod(sp["shape"])) for sp in specs]
+    log(f"generating {len(specs)} fields ({4 * sum(ns) / 1e9:.2f} GB) on the GPU")
+    arena, xs = synth.batch_arena(specs, dev)
+    ebs = [sp["rel_eb"] * synth.value_range(x) for sp, x in zip(specs, xs)]
+    caps = [(hz.batch_out_cap(n, 0) + 15) // 16 * 16 for n in ns]
+    out_arena = torch.empty(sum(caps), dtype=torch.uint8, device=dev)
+    outs, o = [], 0
+    for c in caps:
+        outs.append(out_arena[o:o + c])
+        o += c
+    torch.cuda.synchronize()
+    log("planning (autotuning block sizes and grid)")
+    t0 = time.perf_counter()
+    b = hz.Batch([(xs[i], ebs[i], 0, outs[i]) for i in range(len(xs))], tune_grid=True)
+    plan_s = time.perf_counter() - t0
+    info = b.info()
+    for _ in range(args.warmup):
+        b.launch()
+    torch.cuda.synchronize()
+    res = b.results()
+    bad = [i for i, r in enumerate(res) if r["code"] != 0]
+    if bad:
+        raise RuntimeError(f"batch fields failed: {bad[:10]}")
+    tm = Timer(torch)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        tm.run("batch", b.launch)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    res = b.results()
+    us = tm.mean_us("batch")
+    raw = info["raw_bytes"]
+    out_total = sum(r["out_bytes"] for r in res)
+    alg = raw + out_total
+    achieved = alg / us / 1e3
+    blocks = {L: sum(1 for r in res if r["block"] == L) for L in (32, 64, 128)}
+    cpu = None
+    if args.cpu_sample > 0:
+        cpu = cpu_baseline_batch(specs, xs, ebs, res)
+    line = {
+        "metric": "batched compress + mean/variance GB/s (raw)", "value": round(raw / us / 1e3, 1),
+        "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1000.0 * wall / args.steps, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32 bins (f64 quantization, int64/int128 sums)", "data": "synthetic",
+        "config": {"workload": f"batch_{len(specs)}_fields_4KB-64MB_loguniform", "fields": len(specs),
+                   "raw_bytes": raw, "stream_bytes": out_total, "cr": round(raw / out_total, 3),
+                   "total_tiles": info["total_tiles"], "grid": info["grid"],
+                   "blocks_chosen": blocks, "plan_seconds": round(plan_s, 2),
+                   "parallelism": "single_gpu"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_batch", "launches_per_step": 1, "bytes_per_launch": alg,
+                     "us_per_launch": round(us, 2), "events_include": "the kernel alone"},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline_batch(specs, xs, ebs, res, budget_s=15.0):
+    """The oracle on a seeded random sample of the batch's fields (compress at
+    the block the plan chose, then mean and variance), until ~budget_s."""
+    import numpy as np
+
+    from oracle import ref
+
+    order = np.random.default_rng(8).permutation(len(specs))
+    raw, nf, sec = 0, 0, 0.0
+    for i in order:
+        if sec > budget_s:
+            break
+        x = xs[i].cpu().numpy()
+        t0 = time.perf_counter()
+        c = ref.compress(x, ebs[i], res[i]["block"])
+        ref.mean(c)
+        ref.variance(c)
+        sec += time.perf_counter() - t0
+        raw += 4 * x.size
+        nf += 1
+    return {"value": round(raw / sec / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"{nf} fields drawn at random (seed 8) from the batch, "
+                      f"{raw / 1e6:.0f} MB raw, compress + mean + variance ({sec:.1f} s)"}
 
 
 KERNEL_OF = {"compress": "k_compress<1>", "decompress": "k_decode<2>", "mean": "k_decode<0>",

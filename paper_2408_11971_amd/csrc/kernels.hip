@@ -27,7 +27,8 @@ constexpr double kBinMaxD = 2147483647.0;
 constexpr uint64_t kLbAgg = 1, kLbInc = 2;
 constexpr uint64_t kLbValMask = (uint64_t(1) << 34) - 1;
 constexpr uint32_t kNone = 0xffffffffu;
-constexpr uint32_t kEpochLimit = 1u << 28;  // look-back epochs are 28-bit, never 0
+constexpr uint32_t kEpochLimit = 1u << 28;
+  // look-back epochs are 28-bit, never 0
 
 enum { kMean = 0, kVariance = 1, kDecompress = 2 };
 // context counters (Scratch::ctrl) and accumulators (Scratch::acc)
@@ -98,14 +99,15 @@ __device__ __forceinline__ bool finish_arrive(uint32_t* counter, uint32_t* s_fla
   return uni32(*s_flag) != 0;
 }
 
-// finish_arrive for a counter that reaches `total` arrivals.
-__device__ __forceinline__ bool finish_arrive_n(uint32_t* counter, uint32_t total, uint32_t* s_flag) {
+// finish_arrive for a counter that reaches `total`, adding `count` arrivals.
+__device__ __forceinline__ bool finish_arrive_n(uint32_t* counter, uint32_t count, uint32_t total,
+                                                uint32_t* s_flag) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
     const uint32_t old =
-        __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    *s_flag = old == total - 1 ? 1u : 0u;
+        __hip_atomic_fetch_add(counter, count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    *s_flag = old + count == total ? 1u : 0u;
   }
   __syncthreads();
   return uni32(*s_flag) != 0;
@@ -221,16 +223,25 @@ struct LbShared {
 };
 
 // Decoupled look-back: exclusive prefix over tiles of the per-tile `agg`.
-// The tile publishes its aggregate first, so waiting tiles never block the
-// tiles before them.  Phase 1: wave 0 spins on the 64 nearest predecessors
-// until all have published; if none holds an inclusive prefix, phase 2 reads
-// the next older windows of kThreads tiles with the whole workgroup (one word
-// per thread), so the inclusive-prefix frontier advances hundreds of tiles
-// per device-coherent load instead of 64.  Contains barriers.
-__device__ __forceinline__ uint64_t wg_lookback(uint64_t* st, uint64_t tile, uint64_t agg, uint32_t epoch,
-                                LbShared& sh) {
+// lb_publish stores the tile's aggregate as soon as it is known, so tiles
+// waiting on it never block the tiles before them; the caller can then do
+// work that needs no offset before calling lb_wait.  Phase 1: wave 0 polls
+// the 64 nearest predecessors until every tile up to the nearest inclusive
+// prefix has published.  Phase 2 (only when none of them holds an inclusive
+// prefix): the whole workgroup reads older windows of kThreads status words,
+// one per thread, so the search moves hundreds of tiles per device-coherent
+// load.  (Also storing the inclusive prefix of every summed predecessor, to
+// keep the frontier close, was measured slower on MI355X: the extra
+// device-scope stores cost more than the shorter searches save.)
+__device__ __forceinline__ void lb_publish(uint64_t* st, uint64_t tile, uint64_t agg,
+                                           uint32_t epoch) {
+  if (threadIdx.x == 0) st_dev(&st[tile], lb_word(epoch, tile == 0 ? kLbInc : kLbAgg, agg));
+}
+
+// Contains barriers (except for tile 0, which returns at once).
+__device__ __forceinline__ uint64_t lb_wait(uint64_t* st, uint64_t tile, uint64_t agg,
+                                            uint32_t epoch, LbShared& sh) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  if (tid == 0) st_dev(&st[tile], lb_word(epoch, tile == 0 ? kLbInc : kLbAgg, agg));
   if (tile == 0) return 0;
   if (wave == 0) {
     const int64_t idx = int64_t(tile) - 1 - lane;
@@ -264,7 +275,7 @@ __device__ __forceinline__ uint64_t wg_lookback(uint64_t* st, uint64_t tile, uin
   const bool found = uni32(sh.near_found) != 0;
   __syncthreads();
   if (!found) {
-    int64_t base = int64_t(tile) - 64;  // window covers tiles base-1-tid
+    int64_t base = int64_t(tile) - 64;  // the window covers tiles base-1-tid
     for (;;) {
       const int64_t idx = base - 1 - tid;
       uint32_t fi = kNone, fw = kNone;
@@ -289,9 +300,9 @@ __device__ __forceinline__ uint64_t wg_lookback(uint64_t* st, uint64_t tile, uin
       fi = kNone;
       fw = kNone;
 #pragma unroll
-      for (int v = 0; v < kThreads / 64; ++v) {
-        fi = min(fi, sh.first_inc[v]);
-        fw = min(fw, sh.first_wait[v]);
+      for (int k = 0; k < kThreads / 64; ++k) {
+        fi = min(fi, sh.first_inc[k]);
+        fw = min(fw, sh.first_wait[k]);
       }
       fi = uni32(fi);
       fw = uni32(fw);
@@ -305,7 +316,7 @@ __device__ __forceinline__ uint64_t wg_lookback(uint64_t* st, uint64_t tile, uin
       __syncthreads();
       uint64_t total = 0;
 #pragma unroll
-      for (int v = 0; v < kThreads / 64; ++v) total += sh.part[v];
+      for (int k = 0; k < kThreads / 64; ++k) total += sh.part[k];
       __syncthreads();
       excl += uni64(total);
       if (fi != kNone) break;
@@ -314,6 +325,12 @@ __device__ __forceinline__ uint64_t wg_lookback(uint64_t* st, uint64_t tile, uin
   }
   if (tid == 0) st_dev(&st[tile], lb_word(epoch, kLbInc, excl + agg));
   return excl;
+}
+
+__device__ __forceinline__ uint64_t wg_lookback(uint64_t* st, uint64_t tile, uint64_t agg,
+                                                uint32_t epoch, LbShared& sh) {
+  lb_publish(st, tile, agg, epoch);
+  return lb_wait(st, tile, agg, epoch, sh);
 }
 
 // Payload word offset of `tile` of a stream from its width pre-pass.  Run by
@@ -663,12 +680,14 @@ struct CompressShared {
 // steps 1-3 and the Fig. 3 sections.  The tile's payload offset comes from
 // the decoupled look-back over `st` (one status word per tile of this field).
 // Returns the payload words of tiles 0..tile (uniform).  Error bits go to
-// `bad`; with STATS the tile's valid bins are added to `sums`.  Contains
+// `bad`; with STATS the tile's valid bins are added to `sums`.  Thread 0
+// takes the workgroup's next ticket from `ticket` into `next`.  Contains
 // barriers.
 template <int SPB, bool STATS>
 __device__ __forceinline__ uint64_t compress_tile(const float* x, uint8_t* out, const Layout& g, double eb,
                                   double inv2e, uint64_t tile, uint64_t* st, uint32_t epoch,
-                                  CompressShared& sh, uint32_t& bad, BinSums& sums) {
+                                  CompressShared& sh, uint32_t& bad, BinSums& sums,
+                                  uint32_t* ticket, uint32_t& next) {
   constexpr uint32_t L = SPB * 32;
   const int tid = threadIdx.x;
   const uint64_t seg = tile * kTileSegs + tid;
@@ -716,11 +735,11 @@ __device__ __forceinline__ uint64_t compress_tile(const float* x, uint8_t* out, 
 
   uint32_t tile_words;
   const uint32_t off = wg_scan(w, tile_words, sh.tmp);
-  const uint64_t base = wg_lookback(st, tile, tile_words, epoch, sh.lb);
+  // Publish the tile's payload size as soon as it is known, then do all work
+  // that does not need the tile's offset (packing into LDS, the width,
+  // outlier and sign sections) before waiting on the predecessors.
+  lb_publish(st, tile, tile_words, epoch);
   if (w > 0) pack32(&sh.pay[off], mag, w);
-  __syncthreads();
-  uint32_t* P = reinterpret_cast<uint32_t*>(out + g.off_p) + base;
-  for (uint32_t k = tid; k < tile_words; k += kThreads) P[k] = bswap32(sh.pay[k]);
   if (active) {
     if (sub == 0) {
       out[g.off_w + blk] = uint8_t(w);
@@ -728,6 +747,13 @@ __device__ __forceinline__ uint64_t compress_tile(const float* x, uint8_t* out, 
     }
     reinterpret_cast<uint32_t*>(out + g.off_s)[seg] = bswap32(sgn);
   }
+  const uint64_t base = lb_wait(st, tile, tile_words, epoch, sh.lb);
+  // The next tile is requested now: its ticket is held only while this tile
+  // stores, never while this tile waits on its predecessors.
+  if (tid == 0) next = atomicAdd(ticket, 1u);
+  __syncthreads();
+  uint32_t* P = reinterpret_cast<uint32_t*>(out + g.off_p) + base;
+  for (uint32_t k = tid; k < tile_words; k += kThreads) P[k] = bswap32(sh.pay[k]);
   if (tid == 0 && tile == g.ntiles - 1) write_header(out, g, 4 * (base + tile_words));
   __syncthreads();
   return base + tile_words;
@@ -738,7 +764,7 @@ __global__ void __launch_bounds__(kThreads) k_compress(CompressParams p) {
   __shared__ CompressShared sh;
   const int tid = threadIdx.x;
   const Layout& g = p.g;
-  uint32_t next = 0, bad = 0;
+  uint32_t bad = 0, next = 0;
   BinSums none;
   if (tid == 0) next = atomicAdd(&p.s.ctrl[C_TICKET], 1u);
   for (;;) {
@@ -746,9 +772,9 @@ __global__ void __launch_bounds__(kThreads) k_compress(CompressParams p) {
     __syncthreads();
     const uint64_t tile = uni64(sh.ticket);
     if (tile >= g.ntiles) break;
-    if (tid == 0) next = atomicAdd(&p.s.ctrl[C_TICKET], 1u);  // next tile, fetched early
-    const uint64_t words = compress_tile<SPB, false>(p.x, p.out, g, p.eb, p.inv2e, tile,
-                                                     p.s.st_out, p.epoch, sh, bad, none);
+    const uint64_t words =
+        compress_tile<SPB, false>(p.x, p.out, g, p.eb, p.inv2e, tile, p.s.st_out, p.epoch, sh,
+                                  bad, none, &p.s.ctrl[C_TICKET], next);
     if (tid == 0 && tile == g.ntiles - 1) st_dev(&p.s.acc[A_OUT], g.off_p + 4 * words);
   }
   latch(p.s, bad);
@@ -798,73 +824,93 @@ struct BatchParams {
   hoszp_field_result* res;     // one record per field
 };
 
+// Adds a workgroup's sums and tile count of field f to the field's
+// accumulators; the workgroup that completes the field's tile count writes
+// the field's result record and clears the accumulators.  Contains barriers.
+__device__ __forceinline__ void batch_flush(const BatchParams& p, uint32_t f, const Layout& g,
+                                            BinSums& sums, uint32_t bad, uint32_t count,
+                                            CompressShared& sh) {
+  const int tid = threadIdx.x;
+  wg_sum_s_q(sums.s, sums.ql, sums.qh, sh.rs, sh.rl, sh.rh);
+  bad = uint32_t(__ballot(bad & ST_RANGE) ? ST_RANGE : 0u) |
+        uint32_t(__ballot(bad & ST_NONFINITE) ? ST_NONFINITE : 0u);
+  uint64_t* acc = p.facc + uint64_t(f) * F_WORDS;
+  if ((tid & 63) == 0 && bad) atomicOr(reinterpret_cast<unsigned int*>(&acc[F_STATUS]), bad);
+  if (tid == 0) {
+    atomicAdd(reinterpret_cast<unsigned long long*>(&acc[F_S]), (unsigned long long)sums.s);
+    const uint64_t old = atomicAdd(reinterpret_cast<unsigned long long*>(&acc[F_QLO]),
+                                   (unsigned long long)sums.ql);
+    const uint64_t carry = (old + sums.ql < old) ? 1u : 0u;
+    atomicAdd(reinterpret_cast<unsigned long long*>(&acc[F_QHI]),
+              (unsigned long long)(sums.qh + carry));
+  }
+  if (finish_arrive_n(reinterpret_cast<uint32_t*>(&acc[F_DONE]), count, uint32_t(g.ntiles),
+                      &sh.flag) &&
+      tid == 0) {
+    const uint32_t status = uint32_t(ld_dev(&acc[F_STATUS]));
+    const int64_t S = int64_t(ld_dev(&acc[F_S]));
+    const uint64_t ql = ld_dev(&acc[F_QLO]), qh = ld_dev(&acc[F_QHI]);
+    double mean = 0.0, var = 0.0;
+    if (!status) mean_variance(g.n, g.eb, S, ql, qh, mean, var);
+    hoszp_field_result* r = &p.res[f];
+    r->status = status;
+    r->block = g.L;
+    r->out_bytes = ld_dev(&acc[F_OUT]);
+    r->mean = mean;
+    r->variance = var;
+    for (int k = 0; k < F_WORDS; ++k) acc[k] = 0;
+  }
+  sums = BinSums();
+}
+
 __global__ void __launch_bounds__(kThreads) k_batch(BatchParams p) {
   __shared__ CompressShared sh;
   const int tid = threadIdx.x;
   const uint32_t epoch = uni32(ld_dev32(&p.ctrl[B_EPOCH]));
   uint32_t next = 0;
+  // sums of the tiles this workgroup has done of field cur since the last
+  // flush (consecutive tickets of a workgroup mostly fall in one large field)
+  uint32_t cur = kNone, count = 0, bad = 0;
+  BinSums sums;
+  Layout gc;
   if (tid == 0) next = atomicAdd(&p.ctrl[B_TICKET], 1u);
   for (;;) {
     if (tid == 0) sh.ticket = next;
     __syncthreads();
     const uint64_t t = uni64(sh.ticket);
-    if (t >= p.total_tiles) break;
-    if (tid == 0) next = atomicAdd(&p.ctrl[B_TICKET], 1u);
-    const uint32_t f = uni32(p.tile_field[t]);
+    const uint32_t f = t < p.total_tiles ? uni32(p.tile_field[t]) : kNone;
+    if (f != cur && cur != kNone) {
+      batch_flush(p, cur, gc, sums, bad, count, sh);
+      count = 0;
+      bad = 0;
+    }
+    if (f == kNone) break;
     const BatchField fd = p.fields[f];
     Layout g;
     place(g, fd.n, fd.block, fd.eb);
+    cur = f;
+    gc = g;
     const uint64_t tile = t - fd.tile0;
-    uint32_t bad = 0;
-    BinSums sums;
     uint64_t words = 0;
     switch (g.spb) {
       case 1:
         words = compress_tile<1, true>(fd.x, fd.out, g, fd.eb, fd.inv2e, tile, p.st + fd.tile0,
-                                       epoch, sh, bad, sums);
+                                       epoch, sh, bad, sums, &p.ctrl[B_TICKET], next);
         break;
       case 2:
         words = compress_tile<2, true>(fd.x, fd.out, g, fd.eb, fd.inv2e, tile, p.st + fd.tile0,
-                                       epoch, sh, bad, sums);
+                                       epoch, sh, bad, sums, &p.ctrl[B_TICKET], next);
         break;
       default:
         words = compress_tile<4, true>(fd.x, fd.out, g, fd.eb, fd.inv2e, tile, p.st + fd.tile0,
-                                       epoch, sh, bad, sums);
+                                       epoch, sh, bad, sums, &p.ctrl[B_TICKET], next);
         break;
     }
-    wg_sum_s_q(sums.s, sums.ql, sums.qh, sh.rs, sh.rl, sh.rh);
-    // error bits of the whole tile (wave OR, then one atomic per wave)
-    bad = uint32_t(__ballot(bad & ST_RANGE) ? ST_RANGE : 0u) |
-          uint32_t(__ballot(bad & ST_NONFINITE) ? ST_NONFINITE : 0u);
-    uint64_t* acc = p.facc + uint64_t(f) * F_WORDS;
-    if ((tid & 63) == 0 && bad) atomicOr(reinterpret_cast<unsigned int*>(&acc[F_STATUS]), bad);
-    if (tid == 0) {
-      atomicAdd(reinterpret_cast<unsigned long long*>(&acc[F_S]), (unsigned long long)sums.s);
-      const uint64_t old = atomicAdd(reinterpret_cast<unsigned long long*>(&acc[F_QLO]),
-                                     (unsigned long long)sums.ql);
-      const uint64_t carry = (old + sums.ql < old) ? 1u : 0u;
-      atomicAdd(reinterpret_cast<unsigned long long*>(&acc[F_QHI]),
-                (unsigned long long)(sums.qh + carry));
-      if (tile == g.ntiles - 1) st_dev(&acc[F_OUT], g.off_p + 4 * words);
-    }
-    // the field's last outstanding tile publishes its results
-    if (finish_arrive_n(reinterpret_cast<uint32_t*>(&acc[F_DONE]), uint32_t(g.ntiles), &sh.flag) &&
-        tid == 0) {
-      const uint32_t status = uint32_t(ld_dev(&acc[F_STATUS]));
-      const int64_t S = int64_t(ld_dev(&acc[F_S]));
-      const uint64_t ql = ld_dev(&acc[F_QLO]), qh = ld_dev(&acc[F_QHI]);
-      double mean = 0.0, var = 0.0;
-      if (!status) mean_variance(g.n, g.eb, S, ql, qh, mean, var);
-      hoszp_field_result* r = &p.res[f];
-      r->status = status;
-      r->block = g.L;
-      r->out_bytes = ld_dev(&acc[F_OUT]);
-      r->mean = mean;
-      r->variance = var;
-      for (int k = 0; k < F_WORDS; ++k) acc[k] = 0;
-    }
+    ++count;
+    if (tid == 0 && tile == g.ntiles - 1)
+      st_dev(&p.facc[uint64_t(f) * F_WORDS + F_OUT], g.off_p + 4 * words);
   }
-  if (finish_arrive_n(&p.ctrl[B_DONE], gridDim.x, &sh.flag)) {
+  if (finish_arrive_n(&p.ctrl[B_DONE], 1u, gridDim.x, &sh.flag)) {
     const bool wrap = epoch + 1 >= kEpochLimit;  // epochs wrap: clear every status word
     if (wrap)
       for (uint64_t k = tid; k < p.total_tiles; k += kThreads) p.st[k] = 0;
@@ -1290,7 +1336,6 @@ __global__ void __launch_bounds__(kThreads) k_add(AddParams p) {
     __syncthreads();
     const uint64_t tile = uni64(s_ticket);
     if (tile >= ntiles) break;
-    if (tid == 0) next = atomicAdd(&p.s.ctrl[C_TICKET], 1u);
     if (tid < 64) {
       const uint64_t v = tile_offset(p.s.idx[0], tile);
       if (tid == 0) s_base_a = v;
@@ -1388,11 +1433,9 @@ __global__ void __launch_bounds__(kThreads) k_add(AddParams p) {
     const uint32_t w = bitlen32(mx);
     uint32_t tw_z;
     const uint32_t off_z = wg_scan(w, tw_z, s_tmp);  // barriers: all threads done reading s_a
-    const uint64_t base_z = wg_lookback(p.s.st_out, tile, tw_z, p.epoch, s_lb);
+    // publish the output tile's size, then pack and store what needs no offset
+    lb_publish(p.s.st_out, tile, tw_z, p.epoch);
     if (w > 0) pack32(&s_a[off_z], mag, w);
-    __syncthreads();
-    uint32_t* Pz = reinterpret_cast<uint32_t*>(p.out + g.off_p) + base_z;
-    for (uint32_t k = tid; k < tw_z; k += kThreads) Pz[k] = bswap32(s_a[k]);
     if (active) {
       if (sub == 0) {
         p.out[g.off_w + blk] = uint8_t(w);
@@ -1400,6 +1443,11 @@ __global__ void __launch_bounds__(kThreads) k_add(AddParams p) {
       }
       reinterpret_cast<uint32_t*>(p.out + g.off_s)[seg] = bswap32(sgn);
     }
+    const uint64_t base_z = lb_wait(p.s.st_out, tile, tw_z, p.epoch, s_lb);
+    if (tid == 0) next = atomicAdd(&p.s.ctrl[C_TICKET], 1u);
+    __syncthreads();
+    uint32_t* Pz = reinterpret_cast<uint32_t*>(p.out + g.off_p) + base_z;
+    for (uint32_t k = tid; k < tw_z; k += kThreads) Pz[k] = bswap32(s_a[k]);
     if (tid == 0 && tile == g.ntiles - 1) {
       const uint64_t payload = 4 * (base_z + tw_z);
       write_header(p.out, g, payload);
@@ -1457,7 +1505,6 @@ __global__ void __launch_bounds__(kThreads) k_mul(MulParams p) {
     __syncthreads();
     const uint64_t tile = uni64(s_ticket);
     if (tile >= ntiles) break;
-    if (tid == 0) next = atomicAdd(&p.s.ctrl[C_TICKET], 1u);
     if (tid < 64) {
       const uint64_t v = tile_offset(p.s.idx[0], tile);
       if (tid == 0) s_base = v;
@@ -1525,11 +1572,9 @@ __global__ void __launch_bounds__(kThreads) k_mul(MulParams p) {
     const uint32_t wz = bitlen32(mx);
     uint32_t tw_z;
     const uint32_t off_z = wg_scan(wz, tw_z, s_tmp);
-    const uint64_t base_z = wg_lookback(p.s.st_out, tile, tw_z, p.epoch, s_lb);
+    // publish the output tile's size, then pack and store what needs no offset
+    lb_publish(p.s.st_out, tile, tw_z, p.epoch);
     if (wz > 0) pack32(&s_pay[off_z], mag, wz);
-    __syncthreads();
-    uint32_t* Pz = reinterpret_cast<uint32_t*>(p.out + g.off_p) + base_z;
-    for (uint32_t k = tid; k < tw_z; k += kThreads) Pz[k] = bswap32(s_pay[k]);
     if (active) {
       if (sub == 0) {
         p.out[g.off_w + blk] = uint8_t(wz);
@@ -1537,6 +1582,11 @@ __global__ void __launch_bounds__(kThreads) k_mul(MulParams p) {
       }
       reinterpret_cast<uint32_t*>(p.out + g.off_s)[seg] = bswap32(sgn);
     }
+    const uint64_t base_z = lb_wait(p.s.st_out, tile, tw_z, p.epoch, s_lb);
+    if (tid == 0) next = atomicAdd(&p.s.ctrl[C_TICKET], 1u);
+    __syncthreads();
+    uint32_t* Pz = reinterpret_cast<uint32_t*>(p.out + g.off_p) + base_z;
+    for (uint32_t k = tid; k < tw_z; k += kThreads) Pz[k] = bswap32(s_pay[k]);
     if (tid == 0 && tile == g.ntiles - 1) {
       const uint64_t payload = 4 * (base_z + tw_z);
       write_header(p.out, g, payload);

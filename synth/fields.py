@@ -185,3 +185,55 @@ def batch_field(spec) -> np.ndarray:
     r = field.max() - field.min()
     field = field + rng.normal(0.0, 1e-3 * (r if r > 0 else 1.0), size=shape)
     return field.astype(np.float32).ravel()
+
+
+def batch_field_device(spec, device, out=None):
+    """Device-generated field of a batch spec with the same recipe as
+    ``batch_field`` (per-axis sums of three sinusoids, periods 16..4096, plus
+    Gaussian noise at 1e-3 of the range); the noise comes from a torch
+    generator seeded with the spec's seed, so values differ from the host
+    version.  Writes into ``out`` (float32, numel = prod(shape)) if given."""
+    import torch
+
+    rng = np.random.default_rng(spec["seed"])
+    shape = tuple(spec["shape"])
+    field = torch.zeros(shape, dtype=torch.float64, device=device)
+    for axis, m in enumerate(shape):
+        coord = np.arange(m, dtype=np.float64)
+        prof = np.zeros(m)
+        for _ in range(3):
+            period = math.exp(rng.uniform(math.log(16.0), math.log(4096.0)))
+            prof += rng.uniform(0.5, 1.5) * np.sin(2 * math.pi * coord / period
+                                                    + rng.uniform(0, 2 * math.pi))
+        view = [1] * len(shape)
+        view[axis] = m
+        field += torch.from_numpy(prof).to(device).view(view)
+    r = float(field.max().item() - field.min().item())
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(spec["seed"]))
+    noise = torch.randn(shape, generator=gen, dtype=torch.float32, device=device)
+    field += noise.double() * (1e-3 * (r if r > 0 else 1.0))
+    flat = field.view(-1)
+    if out is None:
+        return flat.float()
+    out.copy_(flat)
+    return out
+
+
+def batch_arena(specs, device):
+    """All fields of a batch generated on `device` into one float32 arena,
+    each starting on a 16-byte boundary; returns (arena, [field views])."""
+    import torch
+
+    ns = [int(np.prod(sp["shape"])) for sp in specs]
+    starts, pos = [], 0
+    for n in ns:
+        starts.append(pos)
+        pos += (n + 3) // 4 * 4
+    arena = torch.empty(pos, dtype=torch.float32, device=device)
+    views = []
+    for sp, n, st in zip(specs, ns, starts):
+        x = arena[st:st + n]
+        batch_field_device(sp, device, out=x)
+        views.append(x)
+    return arena, views

@@ -176,3 +176,32 @@ def test_batch_rejects_bad_fields(dev):
     with pytest.raises(hz.HoszpError) as e:
         hz.Batch([(x, 0.1, 48, out)])
     assert e.value.code == hz.ERR_ARG
+
+
+def test_batch_full_size_sampled(dev):
+    """The 4096-field batch (log-uniform 4 KB..64 MB, ~29 GB) as the benchmark
+    runs it: every field must succeed, a seeded sample of fields up to 2M
+    elements must match the oracle, and the largest fields must match the
+    single-field GPU path (itself pinned to the oracle above)."""
+    print("case batch full size", flush=True)
+    specs = synth.batch_specs(4096, seed=7)
+    _, xs = synth.batch_arena(specs, dev)
+    ebs = [sp["rel_eb"] * synth.value_range(x) for sp, x in zip(specs, xs)]
+    outs = [torch.empty((hz.batch_out_cap(x.numel(), 0) + 15) // 16 * 16, dtype=torch.uint8,
+                        device=dev) for x in xs]
+    b = hz.Batch([(xs[i], ebs[i], 0, outs[i]) for i in range(len(xs))], tune_grid=True)
+    b.launch()
+    res = b.results()
+    assert all(r["code"] == hz.OK for r in res)
+    rng = np.random.default_rng(3)
+    small = [i for i, x in enumerate(xs) if x.numel() <= (1 << 21)]
+    for i in rng.choice(small, size=12, replace=False):
+        x = xs[i].cpu().numpy()
+        c = ref.compress(x, ebs[i], res[i]["block"])
+        assert res[i]["out_bytes"] == c.size, f"field {i}"
+        assert np.array_equal(outs[i][:c.size].cpu().numpy(), c), f"field {i}"
+        assert close(res[i]["mean"], ref.mean(c)) and close(res[i]["variance"], ref.variance(c))
+    for i in sorted(range(len(xs)), key=lambda k: -xs[k].numel())[:3]:
+        c = hz.compress(xs[i], ebs[i], res[i]["block"])
+        assert torch.equal(c, outs[i][:res[i]["out_bytes"]]), f"field {i}"
+        assert hz.mean(c) == res[i]["mean"] and hz.variance(c) == res[i]["variance"]

@@ -1,0 +1,121 @@
+"""Parity at the benchmark's full size: the 512^3 Kolmogorov-spectrum fields
+(134M elements, 16384 tiles of 8192 slots, thousands of tiles in flight at
+once), in the launch configuration the benchmark times.
+
+The oracle cannot compress 537 MB in test time, but blocks are independent:
+compressing a block-aligned slice with the oracle yields exactly that slice's
+widths, outliers, signs and payload bits.  So for seeded random slices (and
+the first and last) the GPU stream's sections must equal the oracle's slice
+stream byte for byte, with the slice's payload found at the offset the GPU
+stream's own widths give.  Mean and variance are checked against exact
+integer sums of the oracle's bins over the whole field; decompression,
+negation, addition and scalar multiplication are checked on the same slices.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import ref
+
+torch = pytest.importorskip("torch")
+import paper_2408_11971_amd as hz  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+N3 = 512
+L = 32
+SLICE = 1 << 16  # elements per sampled slice (2048 blocks)
+
+
+def r16(x):
+    return (x + 15) // 16 * 16
+
+
+def sections(c, n, block):
+    """Section offsets of a stream of n elements in blocks of `block`."""
+    nb = (n + block - 1) // block
+    nseg = nb * (block // 32)
+    off_w = 64
+    off_o = r16(off_w + nb)
+    off_s = r16(off_o + 4 * nb)
+    off_p = r16(off_s + 4 * nseg)
+    return nb, off_w, off_o, off_s, off_p
+
+
+def check_slices(gpu_c, n, slices, oracle_slice):
+    """gpu_c: host bytes of the full GPU stream; oracle_slice(a, b) -> oracle
+    stream of elements [a, b)."""
+    nb, ow, oo, os_, op = sections(gpu_c, n, L)
+    W = gpu_c[ow:ow + nb].astype(np.int64)
+    pay_off = np.concatenate([[0], np.cumsum(W) * (L // 8)])
+    hdr = np.frombuffer(gpu_c[:64].tobytes(), dtype=np.uint64)
+    assert int(hdr[5]) == int(pay_off[-1]), "payload size differs from the widths' sum"
+    for a, b in slices:
+        s = oracle_slice(a, b)
+        snb, sw, so, ss, sp = sections(s, b - a, L)
+        b0 = a // L
+        assert np.array_equal(gpu_c[ow + b0:ow + b0 + snb], s[sw:sw + snb]), f"W [{a},{b})"
+        assert np.array_equal(gpu_c[oo + 4 * b0:oo + 4 * (b0 + snb)], s[so:so + 4 * snb]), \
+            f"O [{a},{b})"
+        assert np.array_equal(gpu_c[os_ + 4 * b0:os_ + 4 * (b0 + snb)], s[ss:ss + 4 * snb]), \
+            f"S [{a},{b})"
+        plen = s.size - sp
+        p0 = op + int(pay_off[b0])
+        assert np.array_equal(gpu_c[p0:p0 + plen], s[sp:]), f"P [{a},{b})"
+
+
+@pytest.fixture(scope="module")
+def fields():
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    dev = torch.device("cuda:0")
+    A = synth.grf_3d(N3, seed=3, device=dev).view(-1)
+    B = synth.grf_3d(N3, seed=4, device=dev).view(-1)
+    return A, B, A.cpu().numpy(), B.cpu().numpy()
+
+
+def sample_slices(n, seed, k=14):
+    rng = np.random.default_rng(seed)
+    starts = sorted(int(s) * L for s in rng.choice((n - SLICE) // L, size=k, replace=False))
+    return [(0, SLICE)] + [(s, s + SLICE) for s in starts] + [(n - SLICE, n)]
+
+
+@pytest.mark.parametrize("rel", [1e-2, 1e-3, 1e-4])
+def test_fullsize_compress_reductions_decompress(fields, rel):
+    print(f"case fullsize compress rel={rel}", flush=True)
+    A, _, a, _ = fields
+    n = a.size
+    eb = rel * synth.value_range(A)
+    c = hz.compress(A, eb, L)
+    gc = c.cpu().numpy()
+    slices = sample_slices(n, 100 + int(-np.log10(rel)))
+    check_slices(gc, n, slices, lambda i, j: ref.compress(a[i:j], eb, L))
+    # exact sums of the oracle's bins over the whole field
+    q = ref.quantize(a, eb).astype(np.int64)
+    S = int(q.sum())
+    assert int(np.abs(q).max()) ** 2 * n < 2**62  # the int64 sum of squares below is exact
+    Q = int((q * q).sum())
+    two = 2.0 * eb
+    mean = (S / n) * two
+    var = ((n * Q - S * S) / n / n) * two * two
+    assert abs(hz.mean(c) - mean) <= 1e-12 * abs(mean) + 1e-300
+    assert abs(hz.variance(c) - var) <= 1e-12 * abs(var)
+    x = hz.decompress(c).cpu().numpy()
+    for i, j in slices:
+        assert np.array_equal(x[i:j], ref.decompress(ref.compress(a[i:j], eb, L))), f"[{i},{j})"
+
+
+@pytest.mark.parametrize("rel", [1e-3])
+def test_fullsize_homomorphic_ops(fields, rel):
+    print(f"case fullsize ops rel={rel}", flush=True)
+    A, B, a, b = fields
+    n = a.size
+    eb = rel * synth.value_range(A)
+    ca = hz.compress(A, eb, L)
+    cb = hz.compress(B, eb, L)
+    slices = sample_slices(n, 7)
+    check_slices(hz.add(ca, cb).cpu().numpy(), n, slices,
+                 lambda i, j: ref.add(ref.compress(a[i:j], eb, L), ref.compress(b[i:j], eb, L)))
+    check_slices(hz.mul(ca, 3.14).cpu().numpy(), n, slices,
+                 lambda i, j: ref.mul(ref.compress(a[i:j], eb, L), 3.14))
+    check_slices(hz.negate(cb).cpu().numpy(), n, slices,
+                 lambda i, j: ref.negate(ref.compress(b[i:j], eb, L)))
