@@ -46,10 +46,16 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=1 << 24,
                     help="elements of each field the oracle is timed on (0 = skip)")
     ap.add_argument("--trad-reps", type=int, default=3)
-    ap.add_argument("--workload", choices=("grf512", "batch"), default="grf512",
+    ap.add_argument("--workload", choices=("grf512", "batch", "serve"), default="grf512",
                     help="grf512: the 512^3 field ops (default); batch: 4096 uneven fields "
-                         "compressed with mean/variance in one captured launch")
+                         "compressed with mean/variance in one captured launch; serve: Poisson "
+                         "query streams over a device store of compressed fields")
     ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--store-gb", type=float, default=40.0)
+    ap.add_argument("--serve-seconds", type=float, default=1.0,
+                    help="arrival window per offered rate")
+    ap.add_argument("--rates", default="1000,5000,20000,50000")
+    ap.add_argument("--slots", type=int, default=8)
     return ap.parse_args()
 
 
@@ -81,6 +87,8 @@ def main():
         sys.exit(2)
     if args.workload == "batch":
         return bench_batch(args)
+    if args.workload == "serve":
+        return bench_serve(args)
     import numpy as np
     import torch
 
@@ -371,6 +379,192 @@ def cpu_baseline_batch(specs, xs, ebs, res, budget_s=15.0):
     return {"value": round(raw / sec / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
             "sample": f"{nf} fields drawn at random (seed 8) from the batch, "
                       f"{raw / 1e6:.0f} MB raw, compress + mean + variance ({sec:.1f} s)"}
+
+
+SERVE_MIX = (("mean", 0.3), ("variance", 0.3), ("add", 0.2), ("negate", 0.1), ("mul", 0.1))
+
+
+def bench_serve(args):
+    """A device store of ~store_gb of compressed fields (replicas of the
+    512^3 fields at the three bounds and of climate-like 1800x3600 steps at
+    blocks 32/64/128, half the bytes each), queried by open-loop Poisson
+    streams (seed 8) at each offered rate for serve_seconds with the mix
+    mean 30 %, variance 30 %, add 20 % (partner from the same field group),
+    negate 10 %, multiply 10 % (scalar U(-2, 2), seed 9), once on the
+    homomorphic path and once on the decompress-compute-recompress path."""
+    import numpy as np
+    import torch
+
+    import paper_2408_11971_amd as hz
+    import synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    base = []  # (stream, header, group)
+    log("building the store: 512^3 fields")
+    for seed in (3, 4):
+        x = synth.grf_3d(512, seed=seed, device=dev).view(-1)
+        if seed == 3:
+            rng3 = synth.value_range(x)
+        for rel in RELS:
+            c = hz.compress(x, rel * rng3, 32).clone()
+            base.append((c, hz.header_of(c), f"grf_{rel:g}"))
+        del x
+    log("building the store: climate-like steps")
+    for t, step in enumerate(synth.climate_steps(4)):
+        xs = torch.from_numpy(step.ravel()).to(dev)
+        eb = 1e-4 * synth.value_range(step)
+        for L in (32, 64, 128):
+            c = hz.compress(xs, eb, L).clone()
+            base.append((c, hz.header_of(c), f"clim{t}_{L}"))
+    target = args.store_gb * 1e9
+    entries = []
+    for kind in ("grf", "clim"):
+        group = [b for b in base if b[2].startswith(kind)]
+        per = sum(int(b[0].numel()) for b in group)
+        reps = max(1, int(round(target / 2 / per)))
+        for r in range(reps):
+            for c, h, g in group:
+                entries.append((c if r == 0 else c.clone(), h, g))
+    torch.cuda.synchronize()
+    store_bytes = sum(int(e[0].numel()) for e in entries)
+    log(f"store: {len(entries)} streams, {store_bytes / 1e9:.1f} GB")
+    ptr = np.array([e[0].data_ptr() for e in entries], dtype=np.uint64)
+    nbytes = np.array([e[1]["total_bytes"] for e in entries], dtype=np.uint64)
+    nel = np.array([e[1]["n"] for e in entries], dtype=np.uint64)
+    blk = np.array([e[1]["block"] for e in entries], dtype=np.uint32)
+    ebs = np.array([e[1]["eb"] for e in entries], dtype=np.float64)
+    groups = {}
+    for i, e in enumerate(entries):
+        groups.setdefault(e[2], []).append(i)
+    gid = [groups[e[2]] for e in entries]
+    ops = [hz.OPS[m[0]] for m in SERVE_MIX]
+    probs = np.array([m[1] for m in SERVE_MIX])
+    rates = [float(r) for r in args.rates.split(",")]
+    rng = np.random.default_rng(8)
+    srng = np.random.default_rng(9)
+    traces = []
+    for lam in rates:
+        gaps = rng.exponential(1.0 / lam, size=int(lam * args.serve_seconds * 1.5) + 16)
+        arr = np.cumsum(gaps)
+        arr = arr[arr < args.serve_seconds]
+        k = arr.size
+        ent = rng.integers(len(entries), size=k)
+        op = np.array(ops)[rng.choice(len(ops), size=k, p=probs)]
+        partner = np.array([gid[e][int(rng.integers(len(gid[e])))] for e in ent])
+        scal = srng.uniform(-2.0, 2.0, size=k)
+        traces.append((lam, arr, ent, op, partner, scal))
+    pool = int(min(48e9, 24 * 4 * int(nel.max())))
+    line_rows = {}
+    qps_hom_top = None
+    alg_hom_top = None
+    for path, pname in ((hz.PATH_HOMOMORPHIC, "homomorphic"),
+                        (hz.PATH_TRADITIONAL, "decompress_compute_recompress")):
+        srv = hz.Server(slots=args.slots, pool_bytes=pool, keep_outputs=False)
+        for lam, arr, ent, op, partner, scal in traces:
+            reqs = srv.make_requests(arr.size)
+            reqs["op"] = op
+            reqs["path"] = path
+            reqs["d_a"] = ptr[ent]
+            reqs["a_bytes"] = nbytes[ent]
+            is_add = op == hz.OP_ADD
+            reqs["d_b"] = np.where(is_add, ptr[partner], 0)
+            reqs["b_bytes"] = np.where(is_add, nbytes[partner], 0)
+            reqs["n"] = nel[ent]
+            reqs["block"] = blk[ent]
+            reqs["eb"] = ebs[ent]
+            reqs["scalar"] = scal
+            reqs["tag"] = np.arange(arr.size)
+            log(f"{pname}: offered {lam:.0f}/s, {arr.size} queries")
+            comps, start = srv.replay(reqs, arr)
+            if (comps["code"] != 0).any():
+                raise RuntimeError(f"{pname}: {(comps['code'] != 0).sum()} queries failed")
+            lat = comps["done_s"] - (start + arr)
+            span = float(comps["done_s"].max() - start)
+            qps = arr.size / span
+            row = {"offered_qps": lam, "queries": int(arr.size), "achieved_qps": round(qps, 1),
+                   "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 4),
+                   "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 4),
+                   "span_s": round(span, 3)}
+            line_rows.setdefault(f"{lam:.0f}", {})[pname] = row
+            if path == hz.PATH_HOMOMORPHIC and lam == rates[-1]:
+                qps_hom_top = qps
+                # algorithmic bytes of the run: the streams read and written
+                out_b = np.where(op == hz.OP_MEAN, 0, np.where(op == hz.OP_VARIANCE, 0,
+                                                             comps["out_bytes"]))
+                rd = nbytes[ent] + np.where(is_add, nbytes[partner], 0)
+                alg_hom_top = (float(rd.sum() + out_b.sum()), span)
+        st = srv.stats()
+        log(f"{pname}: pool peak {st['pool_peak'] / 1e9:.2f} GB, queue peak {st['queue_peak']}")
+        srv.close()
+    for lam, row in line_rows.items():
+        h, t = row["homomorphic"], row["decompress_compute_recompress"]
+        row["p99_speedup"] = round(t["p99_ms"] / h["p99_ms"], 2)
+        row["qps_ratio"] = round(h["achieved_qps"] / t["achieved_qps"], 2)
+    cpu = None
+    if args.cpu_sample > 0:
+        cpu = cpu_baseline_serve(entries, traces[0])
+    achieved = alg_hom_top[0] / alg_hom_top[1] / 1e9
+    line = {
+        "metric": "serving queries/s at the highest offered rate (homomorphic), with p50/p99 "
+                  "latency vs decompress-compute-recompress",
+        "value": round(qps_hom_top, 1), "unit": "queries/s", "n_gpus": 1,
+        "steps": len(rates), "warmup": 0, "ms_per_step": None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32 bins (f64 quantization, int64/int128 sums)", "data": "synthetic",
+        "config": {"workload": f"serve_store_{store_bytes / 1e9:.0f}GB_poisson",
+                   "store_streams": len(entries), "store_bytes": store_bytes,
+                   "slots": args.slots, "pool_bytes": pool, "seconds_per_rate": args.serve_seconds,
+                   "mix": dict(SERVE_MIX), "parallelism": "single_gpu"},
+        "rates": line_rows,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "all kernels of the run at the highest rate (aggregate)",
+                     "launches_per_step": None, "bytes_per_launch": None,
+                     "us_per_launch": None, "events_include": "host clock over the whole run"},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline_serve(entries, trace, budget_s=15.0):
+    """The oracle answering the first queries of the lowest-rate trace that
+    hit climate-step streams (the 512^3 streams take the oracle seconds per
+    query), until ~budget_s."""
+    import numpy as np
+
+    from oracle import ref
+
+    lam, arr, ent, op, partner, scal = trace
+    host = {}
+    sec, done = 0.0, 0
+    names = {0: "mean", 1: "variance", 2: "negate", 3: "add", 4: "mul"}
+    for k in range(arr.size):
+        if sec > budget_s:
+            break
+        e = int(ent[k])
+        if entries[e][1]["n"] > 10_000_000:
+            continue
+        for i in (e, int(partner[k])):
+            if i not in host:
+                host[i] = entries[i][0].cpu().numpy()
+        t0 = time.perf_counter()
+        o = names[int(op[k])]
+        if o == "mean":
+            ref.mean(host[e])
+        elif o == "variance":
+            ref.variance(host[e])
+        elif o == "negate":
+            ref.negate(host[e])
+        elif o == "add":
+            ref.add(host[e], host[int(partner[k])])
+        else:
+            ref.mul(host[e], float(scal[k]))
+        sec += time.perf_counter() - t0
+        done += 1
+    return {"value": round(done / sec, 2), "unit": "queries/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} queries of the {lam:.0f}/s trace on climate-step streams "
+                      f"({sec:.1f} s)"}
 
 
 KERNEL_OF = {"compress": "k_compress<1>", "decompress": "k_decode<2>", "mean": "k_decode<0>",

@@ -286,6 +286,110 @@ int hoszp_batch_info_get(const hoszp_batch* b, hoszp_batch_info* out);
 /* Release a plan (the caller must have synchronized its launches). */
 int hoszp_batch_destroy(hoszp_batch* b);
 
+/* ---- serving: continuous batching of queries over a device store ------
+ *
+ * A server owns `slots` execution slots (each a context, a stream and a
+ * result record) and a device memory pool of `pool_bytes`.  Queries on
+ * caller-owned compressed streams are queued by hoszp_server_submit; each
+ * hoszp_server_poll admits queued queries, oldest first, into free slots as
+ * soon as the pool can hold their outputs and intermediates (a query that
+ * does not fit may be passed by younger ones that do, unless it has waited
+ * longer than the starvation limit), launches them on the slot's stream, so
+ * admitted queries overlap on the device, and returns finished ones.  The
+ * operations are those of Sec. V (Table II), on either path:
+ *   HOSZP_PATH_HOMOMORPHIC   the homomorphic entry points above;
+ *   HOSZP_PATH_TRADITIONAL   decompress, float32 op, re-compress (Fig. 4a),
+ *                            the comparison workflow.
+ * A query's result does not depend on what runs beside it: every slot has
+ * its own scratch, and each kernel's result is a deterministic function of
+ * its inputs. */
+
+#define HOSZP_OP_MEAN 0u
+#define HOSZP_OP_VARIANCE 1u
+#define HOSZP_OP_NEGATE 2u
+#define HOSZP_OP_ADD 3u
+#define HOSZP_OP_MUL 4u
+#define HOSZP_PATH_HOMOMORPHIC 0u
+#define HOSZP_PATH_TRADITIONAL 1u
+
+typedef struct hoszp_request {
+  uint32_t op;          /* HOSZP_OP_* */
+  uint32_t path;        /* HOSZP_PATH_* */
+  const void* d_a;      /* compressed operand (caller-owned, stays valid until done) */
+  uint64_t a_bytes;
+  const void* d_b;      /* second operand of ADD (same n, block and eb), else NULL */
+  uint64_t b_bytes;
+  uint64_t n;           /* elements of the operands (from their headers) */
+  uint32_t block;       /* block size of the operands */
+  uint32_t reserved;    /* must be 0 */
+  double eb;            /* error bound of the operands (re-compression of the
+                           traditional path) */
+  double scalar;        /* MUL */
+  uint64_t tag;         /* caller's id, returned in the completion */
+} hoszp_request;
+
+typedef struct hoszp_completion {
+  uint64_t tag;
+  int32_t code;         /* HOSZP_OK or the query's error code */
+  uint32_t op;
+  double value;         /* MEAN / VARIANCE */
+  void* d_out;          /* NEGATE / ADD / MUL: output stream in the server's
+                           pool, valid until hoszp_server_release (NULL when
+                           the server was told not to keep outputs) */
+  uint64_t out_bytes;
+  double submit_s;      /* host clock (seconds, server epoch): queued, */
+  double admit_s;       /* launched, */
+  double done_s;        /* and seen finished by a poll */
+} hoszp_completion;
+
+typedef struct hoszp_server_config {
+  uint32_t slots;        /* concurrent queries on the device (1..64) */
+  uint32_t keep_outputs; /* 1: completions own their output until released;
+                            0: outputs are returned to the pool at completion */
+  uint64_t pool_bytes;   /* device memory for outputs and intermediates */
+  double starve_s;       /* a query older than this is never passed (0 = 0.05 s) */
+} hoszp_server_config;
+
+typedef struct hoszp_server_stats {
+  uint64_t submitted, admitted, completed, failed;
+  uint64_t pool_bytes, pool_peak;  /* pool size and its high-water mark */
+  uint64_t queue_peak;             /* longest queue seen */
+} hoszp_server_stats;
+
+typedef struct hoszp_server hoszp_server;
+
+/* Create a server on `device` (allocates the pool, one context, stream and
+ * pinned result record per slot).  ARG for a bad config, NOMEM / DEVICE. */
+int hoszp_server_create(int device, const hoszp_server_config* cfg, hoszp_server** out);
+
+/* Queue a query (never blocks, launches nothing).  ARG for a malformed
+ * query, CAPACITY if its memory need exceeds the whole pool. */
+int hoszp_server_submit(hoszp_server* s, const hoszp_request* req);
+
+/* Admit what fits, launch it, and return up to max_out finished queries
+ * (*n_out of them).  Never blocks. */
+int hoszp_server_poll(hoszp_server* s, hoszp_completion* out, uint32_t max_out, uint32_t* n_out);
+
+/* Number of queries queued or running. */
+uint64_t hoszp_server_pending(const hoszp_server* s);
+
+/* Return a completed query's output stream to the pool. */
+int hoszp_server_release(hoszp_server* s, void* d_out);
+
+/* Open-loop replay: submit reqs[i] at arrival_s[i] seconds after the call
+ * starts (non-decreasing), poll until every query has finished, and write
+ * completion i for reqs[i] (out[i]).  The host thread spins between events.
+ * Latency of query i = out[i].done_s - (start + arrival_s[i]); the call's
+ * start is returned in *start_s on the same clock. */
+int hoszp_server_replay(hoszp_server* s, const hoszp_request* reqs, const double* arrival_s,
+                        uint64_t count, hoszp_completion* out, double* start_s);
+
+int hoszp_server_stats_get(const hoszp_server* s, hoszp_server_stats* out);
+
+/* Wait for every running query, then free everything (outputs still held by
+ * completions are freed with the pool). */
+int hoszp_server_destroy(hoszp_server* s);
+
 /* Block until `stream` is idle and return the code of a result record that
  * an async call filled (also copying it to *h_out when h_out is not NULL). */
 int hoszp_result_wait(hoszp_ctx* ctx, const hoszp_result* d_res, hoszp_result* h_out, void* stream);

@@ -63,6 +63,32 @@ class BatchInfo(ctypes.Structure):
 
 BATCH_TUNE_GRID = 1
 
+OP_MEAN, OP_VARIANCE, OP_NEGATE, OP_ADD, OP_MUL = range(5)
+PATH_HOMOMORPHIC, PATH_TRADITIONAL = 0, 1
+OPS = {"mean": OP_MEAN, "variance": OP_VARIANCE, "negate": OP_NEGATE, "add": OP_ADD,
+       "mul": OP_MUL}
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_uint32), ("keep_outputs", ctypes.c_uint32),
+                ("pool_bytes", ctypes.c_uint64), ("starve_s", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint64) for k in ("submitted", "admitted", "completed", "failed",
+                                               "pool_bytes", "pool_peak", "queue_peak")]
+
+
+def _np_dtypes():
+    import numpy as np
+    req = np.dtype([("op", "<u4"), ("path", "<u4"), ("d_a", "<u8"), ("a_bytes", "<u8"),
+                    ("d_b", "<u8"), ("b_bytes", "<u8"), ("n", "<u8"), ("block", "<u4"),
+                    ("reserved", "<u4"), ("eb", "<f8"), ("scalar", "<f8"), ("tag", "<u8")])
+    cpl = np.dtype([("tag", "<u8"), ("code", "<i4"), ("op", "<u4"), ("value", "<f8"),
+                    ("d_out", "<u8"), ("out_bytes", "<u8"), ("submit_s", "<f8"),
+                    ("admit_s", "<f8"), ("done_s", "<f8")])
+    return req, cpl
+
 _LIB = None
 _VP, _SZ, _U64, _U32, _DBL, _INT = (ctypes.c_void_p, ctypes.c_size_t, ctypes.c_uint64,
                                     ctypes.c_uint32, ctypes.c_double, ctypes.c_int)
@@ -100,6 +126,14 @@ _SIGNATURES = {
     "hoszp_batch_device_results": (_VP, [_VP]),
     "hoszp_batch_info_get": (_INT, [_VP, ctypes.POINTER(BatchInfo)]),
     "hoszp_batch_destroy": (_INT, [_VP]),
+    "hoszp_server_create": (_INT, [_INT, ctypes.POINTER(ServerConfig), ctypes.POINTER(_VP)]),
+    "hoszp_server_submit": (_INT, [_VP, _VP]),
+    "hoszp_server_poll": (_INT, [_VP, _VP, _U32, ctypes.POINTER(_U32)]),
+    "hoszp_server_pending": (_U64, [_VP]),
+    "hoszp_server_release": (_INT, [_VP, _VP]),
+    "hoszp_server_replay": (_INT, [_VP, _VP, _VP, _U64, _VP, ctypes.POINTER(_DBL)]),
+    "hoszp_server_stats_get": (_INT, [_VP, ctypes.POINTER(ServerStats)]),
+    "hoszp_server_destroy": (_INT, [_VP]),
 }
 
 
@@ -443,6 +477,106 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------- serving
+
+class Server:
+    """Continuous-batching query server (see hoszp_server_create).
+
+    Requests are numpy records of ``request_dtype`` (build them with
+    ``make_requests``); completions come back as records of
+    ``completion_dtype``."""
+
+    def __init__(self, device=0, slots=8, pool_bytes=1 << 30, keep_outputs=False, starve_s=0.0):
+        self.request_dtype, self.completion_dtype = _np_dtypes()
+        cfg = ServerConfig(slots, 1 if keep_outputs else 0, pool_bytes, starve_s)
+        h = _VP()
+        _check(_lib().hoszp_server_create(device, ctypes.byref(cfg), ctypes.byref(h)),
+               "server_create")
+        self.handle = h
+
+    def make_requests(self, count):
+        import numpy as np
+        return np.zeros(count, dtype=self.request_dtype)
+
+    def submit(self, reqs):
+        import numpy as np
+        reqs = np.ascontiguousarray(reqs, dtype=self.request_dtype).reshape(-1)
+        for i in range(reqs.size):
+            _check(_lib().hoszp_server_submit(self.handle, reqs[i:i + 1].ctypes.data),
+                   "server_submit")
+
+    def poll(self, max_out=256):
+        import numpy as np
+        out = np.zeros(max_out, dtype=self.completion_dtype)
+        n = _U32(0)
+        _check(_lib().hoszp_server_poll(self.handle, out.ctypes.data, max_out, ctypes.byref(n)),
+               "server_poll")
+        return out[:n.value]
+
+    def pending(self) -> int:
+        return _lib().hoszp_server_pending(self.handle)
+
+    def drain(self):
+        """Poll until nothing is queued or running; returns every completion."""
+        import numpy as np
+        got = []
+        while True:
+            c = self.poll()
+            if c.size:
+                got.append(c)
+            elif self.pending() == 0:
+                break
+        return np.concatenate(got) if got else np.zeros(0, dtype=self.completion_dtype)
+
+    def replay(self, reqs, arrival_s):
+        """Open-loop replay; returns (completions in request order, start time)."""
+        import numpy as np
+        reqs = np.ascontiguousarray(reqs, dtype=self.request_dtype).reshape(-1)
+        arr = np.ascontiguousarray(arrival_s, dtype=np.float64).reshape(-1)
+        out = np.zeros(reqs.size, dtype=self.completion_dtype)
+        start = _DBL(0.0)
+        _check(_lib().hoszp_server_replay(self.handle, reqs.ctypes.data, arr.ctypes.data, reqs.size,
+                                          out.ctypes.data, ctypes.byref(start)), "server_replay")
+        return out, start.value
+
+    def release(self, d_out):
+        _check(_lib().hoszp_server_release(self.handle, _VP(int(d_out))), "server_release")
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(_lib().hoszp_server_stats_get(self.handle, ctypes.byref(st)), "server_stats")
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None) and _LIB is not None:
+            _LIB.hoszp_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fill_request(rec, op, a, b=None, scalar=0.0, path=PATH_HOMOMORPHIC, tag=0, info=None):
+    """Fill one request record for stream tensor `a` (and `b` for add);
+    `info` is a parsed header of `a` (read from the device when omitted)."""
+    h = info or header_of(a)
+    rec["op"] = OPS[op] if isinstance(op, str) else op
+    rec["path"] = path
+    rec["d_a"] = a.data_ptr()
+    rec["a_bytes"] = h["total_bytes"]
+    if b is not None:
+        rec["d_b"] = b.data_ptr()
+        rec["b_bytes"] = h["total_bytes"] if b is a else header_of(b)["total_bytes"]
+    rec["n"] = h["n"]
+    rec["block"] = h["block"]
+    rec["eb"] = h["eb"]
+    rec["scalar"] = scalar
+    rec["tag"] = tag
 
 
 def result_struct_size() -> int:

@@ -112,3 +112,25 @@ def test_batch_out_cap_covers_every_block(lib):
         cap = hz.batch_out_cap(n)
         assert cap == max(ref.bound(n, L) for L in (32, 64, 128))
         assert hz.batch_out_cap(n, 64) == ref.bound(n, 64)
+
+
+def test_server_structs_match_header(lib):
+    import ctypes
+    req, cpl = hz._np_dtypes()
+    assert req.itemsize == 80 and cpl.itemsize == 64
+    assert ctypes.sizeof(hz.ServerConfig) == 24
+    assert ctypes.sizeof(hz.ServerStats) == 56
+
+
+def test_server_rejects_bad_config_without_device(lib):
+    import ctypes
+    h = ctypes.c_void_p()
+    bad = [hz.ServerConfig(0, 0, 1 << 20, 0.0), hz.ServerConfig(65, 0, 1 << 20, 0.0),
+           hz.ServerConfig(4, 0, 0, 0.0), hz.ServerConfig(4, 2, 1 << 20, 0.0),
+           hz.ServerConfig(4, 0, 1 << 20, -1.0)]
+    for cfg in bad:
+        assert lib.hoszp_server_create(0, ctypes.byref(cfg), ctypes.byref(h)) == hz.ERR_ARG
+    assert lib.hoszp_server_create(0, None, ctypes.byref(h)) == hz.ERR_ARG
+    assert lib.hoszp_server_submit(None, None) == hz.ERR_ARG
+    assert lib.hoszp_server_pending(None) == 0
+    assert lib.hoszp_server_destroy(None) == hz.OK
