@@ -188,10 +188,11 @@ int hoszp_ctx_create(int device, hoszp_ctx** out) {
     return HOSZP_ERR_DEVICE;
   }
   auto up = [](size_t b) { return (b + 255) / 256 * 256; };  // every array 256-byte aligned
-  const size_t nchunk = kMaxTiles / hz::kChunkTiles + 2;
+  const size_t max_wtiles = size_t(kMaxTiles) * hz::kWavesPerTile;
+  const size_t nchunk = max_wtiles / hz::kChunkTiles + 2;
   const size_t ctrl_b = 256, acc_b = 256, part_b = up(size_t(kMaxPart) * sizeof(double));
   const size_t st_b = up(size_t(kMaxTiles) * sizeof(uint64_t));
-  const size_t off_b = up(nchunk * sizeof(uint64_t)), tw_b = up(size_t(kMaxTiles) * sizeof(uint32_t));
+  const size_t off_b = up(nchunk * sizeof(uint64_t)), tw_b = up(max_wtiles * sizeof(uint32_t));
   const size_t cw_b = up(nchunk * sizeof(uint32_t));
   const size_t idx_b = off_b + tw_b + cw_b;
   const size_t bytes = ctrl_b + acc_b + part_b + st_b + 2 * idx_b + up(sizeof(hoszp_result));

@@ -25,6 +25,17 @@ constexpr int kThreads = 256;
 constexpr int kTileSegs = kThreads;
 constexpr int kTileWords = kTileSegs * 32;  // worst-case payload words of a tile
 
+// Decoders work per wave on "wave tiles" of kWaveSegs segments (2048 slots),
+// with no workgroup barrier between tiles.  The width pre-pass stores every
+// wave tile's payload word count and, for every chunk of kChunkTiles wave
+// tiles, the exclusive prefix; a wave tile's offset is its chunk's prefix
+// plus at most 63 counts (one wave-wide load).  A workgroup tile (kTileSegs
+// segments) of the encoders is kTileSegs / kWaveSegs consecutive wave tiles.
+constexpr int kWaveSegs = 64;
+constexpr int kWaveWords = kWaveSegs * 32;  // worst-case payload words of a wave tile
+constexpr int kWavesPerTile = kTileSegs / kWaveSegs;
+constexpr int kChunkTiles = 64;
+
 // ---- status bits latched by the kernels (bit = 1 << code) -----------------
 constexpr uint32_t ST_ARG = 1u << HOSZP_ERR_ARG;
 constexpr uint32_t ST_NONFINITE = 1u << HOSZP_ERR_NONFINITE;
@@ -35,7 +46,7 @@ constexpr uint32_t ST_CAPACITY = 1u << HOSZP_ERR_CAPACITY;
 
 // Section placement of a stream with n elements in blocks of L.
 struct Layout {
-  uint64_t n, nb, nseg, ntiles;
+  uint64_t n, nb, nseg, ntiles, nwtiles;  // nwtiles: wave tiles
   uint32_t L, spb;  // block size, segments per block
   double eb;
   uint64_t off_w, off_o, off_s, off_p;
@@ -53,6 +64,7 @@ __host__ __device__ inline void place(Layout& g, uint64_t n, uint32_t L, double 
   g.nb = (n + L - 1) / L;
   g.nseg = g.nb * g.spb;
   g.ntiles = (g.nseg + kTileSegs - 1) / kTileSegs;
+  g.nwtiles = (g.nseg + kWaveSegs - 1) / kWaveSegs;
   g.off_w = kHeaderBytes;
   g.off_o = round16(g.off_w + g.nb);
   g.off_s = round16(g.off_o + 4 * g.nb);
@@ -68,15 +80,11 @@ __host__ __device__ inline uint64_t bound_bytes(uint64_t n, uint32_t L) {
   return g.off_p + 4 * uint64_t(L) * g.nb;
 }
 
-// Tiles are grouped in chunks of kChunkTiles for the width pre-pass: the
-// pre-pass stores every tile's payload word count and the exclusive prefix
-// of every chunk; a tile's offset is its chunk's prefix plus at most 63 tile
-// counts (one wave-wide load).
-constexpr int kChunkTiles = 64;
+
 
 // Per-stream results of the width pre-pass.
 struct TileIndex {
-  uint32_t* tile_words;   // payload words of every tile
+  uint32_t* tile_words;   // payload words of every wave tile
   uint32_t* chunk_words;  // payload words of every chunk
   uint64_t* chunk_off;    // exclusive prefix of chunk_words
 };
@@ -89,7 +97,7 @@ struct Scratch {
   double* part;         // per-workgroup partials of the float32 reductions
   uint64_t* st_out;     // look-back status words of an output stream
   TileIndex idx[2];     // width pre-pass of input stream A and B
-  uint32_t max_tiles;   // capacity of the per-tile arrays
+  uint32_t max_tiles;   // capacity of the per-tile status words (and / 64 chunks)
   uint32_t max_part;    // capacity of `part`
 };
 

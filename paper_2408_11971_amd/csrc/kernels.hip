@@ -333,8 +333,8 @@ __device__ __forceinline__ uint64_t wg_lookback(uint64_t* st, uint64_t tile, uin
   return lb_wait(st, tile, agg, epoch, sh);
 }
 
-// Payload word offset of `tile` of a stream from its width pre-pass.  Run by
-// one whole wave; every lane gets the result.
+// Payload word offset of wave tile `tile` of a stream from its width
+// pre-pass.  Run by one whole wave; every lane gets the result.
 __device__ __forceinline__ uint64_t tile_offset(const TileIndex& ix, uint64_t tile) {
   const int lane = threadIdx.x & 63;
   const uint64_t chunk = tile / kChunkTiles;
@@ -506,46 +506,53 @@ struct WidthParams {
   Scratch s;
 };
 
-// Sum of the widths of the 4 segments 4*lane .. 4*lane+3 of a tile, each
-// segment counting its block's width; also flags widths above 32.
-__device__ __forceinline__ uint32_t widths_of_quad(const uint8_t* c, const Layout& g, uint64_t tile,
-                                                   int lane, uint32_t& bad) {
-  const uint64_t seg0 = tile * kTileSegs + 4 * uint64_t(lane);
+// Payload words of the 16 segments seg0 .. seg0+15 (those below nseg): each
+// segment counts its block's width.  Widths above 32 are flagged (and
+// counted as 0).  seg0 is a multiple of 16, so the width bytes are aligned.
+__device__ __forceinline__ uint32_t widths_of_16(const uint8_t* c, const Layout& g, uint64_t seg0,
+                                                 uint32_t& bad) {
   if (seg0 >= g.nseg) return 0;
   const uint8_t* W = c + g.off_w;
-  uint32_t packed, n;  // packed width bytes and their multiplicity
-  if (g.spb == 1) {
-    if (seg0 + 4 <= g.nseg) {
-      packed = *reinterpret_cast<const uint32_t*>(W + seg0);
+  const uint64_t b0 = seg0 / g.spb;               // first block
+  const uint64_t nbk = 16 / g.spb;                // blocks covered when whole
+  const uint64_t have = g.nb - b0 < nbk ? g.nb - b0 : nbk;
+  uint32_t q[4] = {0, 0, 0, 0};
+  if (have == nbk) {
+    if (nbk == 16) {
+      const uint4 v = *reinterpret_cast<const uint4*>(W + b0);
+      q[0] = v.x, q[1] = v.y, q[2] = v.z, q[3] = v.w;
+    } else if (nbk == 8) {
+      const uint2 v = *reinterpret_cast<const uint2*>(W + b0);
+      q[0] = v.x, q[1] = v.y;
     } else {
-      packed = 0;
-      for (uint32_t q = 0; seg0 + q < g.nseg; ++q) packed |= uint32_t(W[seg0 + q]) << (8 * q);
+      q[0] = *reinterpret_cast<const uint32_t*>(W + b0);
     }
-    n = 1;
-  } else if (g.spb == 2) {  // nseg is even: the quad holds one or two whole blocks
-    packed = seg0 + 4 <= g.nseg ? *reinterpret_cast<const uint16_t*>(W + seg0 / 2) : W[seg0 / 2];
-    n = 2;
   } else {
-    packed = W[seg0 / 4];
-    n = 4;
+    for (uint32_t k = 0; k < uint32_t(have); ++k) q[k >> 2] |= uint32_t(W[b0 + k]) << (8 * (k & 3));
   }
-  // a byte b > 32 has its top bit set or carries b + 95 into bit 7
-  if ((packed | ((packed & 0x7f7f7f7fu) + 0x5f5f5f5fu)) & 0x80808080u) {
-    bad |= ST_FORMAT;
-    uint32_t ok = 0;
-    for (int q = 0; q < 4; ++q) {
-      const uint32_t b = (packed >> (8 * q)) & 0xffu;
-      ok |= (b <= 32 ? b : 0u) << (8 * q);
+  uint32_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    uint32_t packed = q[k];
+    // a byte b > 32 has its top bit set or carries b + 95 into bit 7
+    if ((packed | ((packed & 0x7f7f7f7fu) + 0x5f5f5f5fu)) & 0x80808080u) {
+      bad |= ST_FORMAT;
+      uint32_t ok = 0;
+      for (int t = 0; t < 4; ++t) {
+        const uint32_t v = (packed >> (8 * t)) & 0xffu;
+        ok |= (v <= 32 ? v : 0u) << (8 * t);
+      }
+      packed = ok;
     }
-    packed = ok;
+    sum = __builtin_amdgcn_sad_u8(packed, 0u, sum);  // adds the 4 bytes
   }
-  return n * __builtin_amdgcn_sad_u8(packed, 0u, 0u);  // sum of the 4 bytes
+  return sum * g.spb;
 }
 
 // Width pre-pass of a stream (reads only its width section): payload words of
-// every tile and the exclusive prefix of every chunk of kChunkTiles tiles, so
-// decoders locate any tile's payload without a serial scan.  Also checks
-// every width <= 32 and that the widths fill the payload exactly.
+// every wave tile and the exclusive prefix of every chunk of kChunkTiles wave
+// tiles, so decoders locate any tile's payload without a serial scan.  Also
+// checks every width <= 32 and that the widths fill the payload exactly.
 __global__ void __launch_bounds__(kThreads) k_widths(WidthParams p) {
   __shared__ uint32_t s_chunk[kThreads / 64];
   __shared__ uint64_t s_tmp[kThreads / 64];
@@ -557,26 +564,23 @@ __global__ void __launch_bounds__(kThreads) k_widths(WidthParams p) {
     if (tid == 0 && blockIdx.x == 0) latch(p.s, err);
     return;
   }
-  const uint64_t nchunks = (g.ntiles + kChunkTiles - 1) / kChunkTiles;
-  constexpr int kTilesPerWave = kChunkTiles / (kThreads / 64);
+  static_assert(kChunkTiles * kWaveSegs == kThreads * 16, "16 segments per thread per chunk");
+  const uint64_t nchunks = (g.nwtiles + kChunkTiles - 1) / kChunkTiles;
   uint32_t bad = 0;
   for (uint64_t chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
-    const uint64_t t0 = chunk * kChunkTiles + uint64_t(wave) * kTilesPerWave;
-    uint32_t v[kTilesPerWave];
-#pragma unroll
-    for (int k = 0; k < kTilesPerWave; ++k) v[k] = widths_of_quad(p.c, g, t0 + k, lane, bad);
-    uint32_t csum = 0;
-#pragma unroll
-    for (int k = 0; k < kTilesPerWave; ++k) {
-      const uint32_t t = wave_sum32(v[k]);
-      if (lane == k && t0 + k < g.ntiles) p.ix.tile_words[t0 + k] = t;
-      csum += t;
-    }
-    if (lane == 0) s_chunk[wave] = csum;
+    // thread tid: segments 16 tid .. 16 tid + 15 of the chunk, a quarter of
+    // wave tile tid / 4
+    uint32_t v = widths_of_16(p.c, g, chunk * (kChunkTiles * kWaveSegs) + 16 * uint64_t(tid), bad);
+    v += __shfl_xor(v, 1, 64);
+    v += __shfl_xor(v, 2, 64);
+    const uint64_t wt = chunk * kChunkTiles + uint64_t(tid >> 2);
+    if ((tid & 3) == 0 && wt < g.nwtiles) p.ix.tile_words[wt] = v;
+    const uint32_t wsum = wave_sum32((tid & 3) == 0 ? v : 0u);
+    if (lane == 0) s_chunk[wave] = wsum;
     __syncthreads();
     if (tid == 0) {
       uint32_t t = 0;
-      for (int v2 = 0; v2 < kThreads / 64; ++v2) t += s_chunk[v2];
+      for (int k = 0; k < kThreads / 64; ++k) t += s_chunk[k];
       st_dev32(&p.ix.chunk_words[chunk], t);
     }
     __syncthreads();
@@ -942,35 +946,25 @@ __device__ __forceinline__ uint32_t weighted_popcount(uint32_t v) {
 // sum_i (32 - i) d_i.  With x_i = m_i XOR (-s_i) = d_i - s_i (s_i the sign
 // bit, slot i at bit 31 - i of `signs`):
 // E = sum_i (32 - i) x_i + sum_{i: s_i} (32 - i), all in 32-bit integers.
+// The same pass also yields D = the delta total (sum_i x_i + popcount(signs),
+// slot 0 of a block excluded).
 __device__ __forceinline__ int32_t mean_fast(const uint32_t* sp, uint32_t w, uint32_t signs,
-                                             bool first_seg) {
+                                             bool first_seg, int32_t& D) {
   const uint32_t rs = 32u - w;
-  int32_t acc = 0;
+  int32_t acc = 0, tot = 0;
   uint32_t pbit = 0;
 #pragma unroll
   for (int j = 0; j < 32; ++j) {
     const int32_t m = int32_t(field_at(sp, pbit, rs));
     pbit += w;
-    const int32_t x = m ^ (int32_t(signs << j) >> 31);
-    const int32_t c = j == 0 ? (first_seg ? 0 : 32) : 32 - j;
+    int32_t x = m ^ (int32_t(signs << j) >> 31);
+    if (j == 0 && first_seg) x = 0;
+    const int32_t c = j == 0 ? 32 : 32 - j;
     acc += __mul24(x, c);
+    tot += x;
   }
+  D = tot + int32_t(__popc(signs));
   return acc + int32_t(weighted_popcount(signs));
-}
-
-// Delta total of a full segment of width 1..20 (signs as in mean_fast).
-__device__ __forceinline__ int32_t delta_total_fast(const uint32_t* sp, uint32_t w,
-                                                    uint32_t signs, bool first_seg) {
-  const uint32_t rs = 32u - w;
-  int32_t tot = 0;
-  uint32_t pbit = 0;
-#pragma unroll
-  for (int j = 0; j < 32; ++j) {
-    const int32_t m = int32_t(field_at(sp, pbit, rs));
-    pbit += w;
-    if (!(j == 0 && first_seg)) tot += m ^ (int32_t(signs << j) >> 31);
-  }
-  return tot + int32_t(__popc(signs));
 }
 
 // Fast path of a full segment (width 1..20) for the variance: E = sum e_j
@@ -1063,44 +1057,145 @@ __device__ __forceinline__ uint32_t stage_tile(const uint8_t* c, const Layout& g
   return off;
 }
 
+// Raw loads of a wave tile's metadata, issued two tiles ahead of use: the
+// lane's block width and outlier, and the tile's payload offset inputs (its
+// chunk's prefix and one per-tile word count per lane).
+struct MetaA {
+  uint32_t w;
+  int32_t outlier;
+  uint32_t tw;       // tile_words[chunk * 64 + lane] when lane < tile % 64
+  uint64_t chunk_off;
+};
+
+// The same tile one step later: scanned widths, sign word and the first
+// payload words, issued one tile ahead of use.
+constexpr int kPrefetchWords = 8;  // payload words per lane held in registers
+struct MetaB {
+  uint32_t w, off, words, sw;
+  int32_t outlier;
+  uint64_t base;
+  uint32_t pf[kPrefetchWords];
+};
+
+__device__ __forceinline__ void meta_a(const Layout& g, const uint8_t* W, const int32_t* O,
+                                       const TileIndex& ix, uint64_t wt, uint64_t nwt,
+                                       MetaA& m) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t seg = wt * kWaveSegs + lane;
+  const bool active = wt < nwt && seg < g.nseg;
+  const uint64_t blk = seg / g.spb;
+  m.w = active ? W[blk] : 0u;
+  m.outlier = active ? O[blk] : 0;
+  const uint64_t chunk = wt / kChunkTiles;
+  const uint32_t r = uint32_t(wt % kChunkTiles);
+  m.tw = (wt < nwt && uint32_t(lane) < r) ? ix.tile_words[chunk * kChunkTiles + lane] : 0u;
+  m.chunk_off = wt < nwt ? ix.chunk_off[chunk] : 0u;
+}
+
+__device__ __forceinline__ void meta_b(const Layout& g, const uint32_t* S, const uint32_t* P,
+                                       uint64_t payload_words, uint64_t wt, uint64_t nwt,
+                                       const MetaA& a, MetaB& m, uint32_t& bad) {
+  const int lane = threadIdx.x & 63;
+  uint32_t w = a.w;
+  if (w > 32) {
+    bad |= ST_FORMAT;
+    w = 0;
+  }
+  const uint64_t seg = wt * kWaveSegs + lane;
+  const uint64_t blk = seg / g.spb;
+  const uint32_t sub = uint32_t(seg % g.spb);
+  uint64_t blen = 0;
+  const uint32_t cnt = (wt < nwt && seg < g.nseg) ? seg_count(g, blk, sub, blen) : 0u;
+  uint32_t x = w;  // inclusive scan of the widths over the wave
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  m.w = w;
+  m.off = x - w;
+  m.words = uni32(__shfl(x, 63, 64));
+  m.outlier = a.outlier;
+  m.base = a.chunk_off + wave_sum(uint64_t(a.tw));
+  m.sw = (cnt > 0 && w > 0) ? S[seg] : 0u;
+  if (m.base + m.words > payload_words) {
+    bad |= ST_FORMAT;
+    m.words = 0;
+  }
+#pragma unroll
+  for (int k = 0; k < kPrefetchWords; ++k) {
+    const uint32_t i = uint32_t(lane) + 64u * k;
+    m.pf[k] = i < m.words ? P[m.base + i] : 0u;
+  }
+}
+
+// Decoders: every wave walks its own wave tiles (64 segments) with a static
+// stride and stages each tile's payload in its own LDS region, so waves never
+// wait on each other.  The loop is software-pipelined: widths, outliers and
+// offsets are loaded two tiles ahead, sign words and the first payload words
+// one tile ahead, so memory latency overlaps the current tile's arithmetic.
 template <int MODE>
 __global__ void __launch_bounds__(kThreads) k_decode(DecodeParams p) {
-  __shared__ uint32_t s_pay[kTileWords + 2];
-  __shared__ uint32_t s_tmp[kThreads / 64];
-  __shared__ uint64_t s_base;
+  __shared__ uint32_t s_pay[kThreads / 64][kWaveWords + 2];
   __shared__ uint32_t s_flag;
   __shared__ int64_t s_rs[kThreads / 64];
   __shared__ uint64_t s_rl[kThreads / 64], s_rh[kThreads / 64];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   Layout g;
   uint32_t err = read_header(p.c, p.c_bytes, g);
   if (!err && MODE == kDecompress && p.n_cap < g.n) err = ST_CAPACITY;
   if (tid == 0 && blockIdx.x == 0) latch(p.s, err);
-  const uint64_t ntiles = err ? 0 : g.ntiles;
+  const uint64_t nwt = err ? 0 : g.nwtiles;
+  const uint8_t* W = p.c + g.off_w;
   const uint32_t* S = reinterpret_cast<const uint32_t*>(p.c + g.off_s);
   const int32_t* O = reinterpret_cast<const int32_t*>(p.c + g.off_o);
+  const uint32_t* P = reinterpret_cast<const uint32_t*>(p.c + g.off_p);
+  const uint64_t payload_words = g.payload_bytes / 4;
+  uint32_t* wp = s_pay[wave];
   const double two_eb = 2.0 * g.eb;
   int64_t acc_s = 0;
   uint64_t acc_ql = 0, acc_qh = 0;
   uint32_t bad = 0;
-  for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    if (tid < 64) {
-      const uint64_t b = tile_offset(p.s.idx[0], tile);
-      if (tid == 0) s_base = b;
+  const uint64_t stride = uint64_t(gridDim.x) * (kThreads / 64);
+  const uint64_t wt0 = uint64_t(blockIdx.x) * (kThreads / 64) + wave;
+  MetaA a1, a2;
+  MetaB b0;
+  if (wt0 < nwt) {
+    MetaA a0;
+    meta_a(g, W, O, p.s.idx[0], wt0, nwt, a0);
+    meta_a(g, W, O, p.s.idx[0], wt0 + stride, nwt, a1);
+    meta_b(g, S, P, payload_words, wt0, nwt, a0, b0, bad);
+  }
+  for (uint64_t wt = wt0; wt < nwt; wt += stride) {
+    meta_a(g, W, O, p.s.idx[0], wt + 2 * stride, nwt, a2);
+    // stage this tile's payload (prefetched words first)
+    const uint32_t words = b0.words;
+#pragma unroll
+    for (int k = 0; k < kPrefetchWords; ++k) {
+      const uint32_t i = uint32_t(lane) + 64u * k;
+      if (i < words) wp[1 + i] = bswap32(b0.pf[k]);
     }
-    uint32_t w, tile_words;
-    const uint32_t off = stage_tile(p.c, g, tile, s_pay, s_tmp, &s_base, w, tile_words, bad);
-    const uint64_t seg = tile * kTileSegs + tid;
+    for (uint32_t i = lane + 64u * kPrefetchWords; i < words; i += 64)
+      wp[1 + i] = bswap32(P[b0.base + i]);
+    if (lane == 0) {
+      wp[0] = 0;
+      wp[1 + words] = 0;
+    }
+    __builtin_amdgcn_wave_barrier();  // LDS operations of one wave complete in order
+    const uint32_t w = b0.w, off = b0.off, sw = bswap32(b0.sw);
+    const int32_t outlier = b0.outlier;
+    // the next tile's sign words and payload are in flight during this tile
+    meta_b(g, S, P, payload_words, wt + stride, nwt, a1, b0, bad);
+    a1 = a2;
+
+    const uint64_t seg = wt * kWaveSegs + lane;
     const bool active = seg < g.nseg;
     const uint64_t blk = seg / g.spb;
     const uint32_t sub = uint32_t(seg % g.spb);
     uint64_t blen = 0;
     const uint32_t cnt = active ? seg_count(g, blk, sub, blen) : 0u;
-    const int32_t outlier = active ? O[blk] : 0;
-    const uint32_t sw = (cnt > 0 && w > 0) ? bswap32(S[seg]) : 0u;
-    __syncthreads();
 
-    const uint32_t* sp = &s_pay[1 + off];
+    const uint32_t* sp = &wp[1 + off];
     const bool fast = cnt == 32 && w <= 20;
     // in-segment sums: D = delta total, E = sum of prefixes, E2 = sum of squares
     int64_t D = 0, E = 0;
@@ -1116,8 +1211,9 @@ __global__ void __launch_bounds__(kThreads) k_decode(DecodeParams p) {
         }
       } else if (MODE == kMean) {
         const uint32_t signs = sub == 0 ? (sw & 0x7fffffffu) : sw;  // slot 0: the outlier
-        E = mean_fast(sp, w, signs, sub == 0);
-        if (g.spb > 1) D = delta_total_fast(sp, w, signs, sub == 0);
+        int32_t d1;
+        E = mean_fast(sp, w, signs, sub == 0, d1);
+        D = d1;
       } else if (MODE == kVariance) {
         int32_t e1, d1;
         int64_t e2;
@@ -1176,7 +1272,7 @@ __global__ void __launch_bounds__(kThreads) k_decode(DecodeParams p) {
         acc_ql = nl;
       }
     }
-    __syncthreads();
+    __builtin_amdgcn_wave_barrier();  // every lane's LDS reads precede the next staging
   }
   latch(p.s, bad);
   double value = 0.0;
@@ -1196,21 +1292,9 @@ __global__ void __launch_bounds__(kThreads) k_decode(DecodeParams p) {
   if (!finish_arrive(&p.s.ctrl[C_DONE], &s_flag)) return;
   if (tid == 0 && !err && MODE != kDecompress) {
     const int64_t S_all = int64_t(ld_dev(&p.s.acc[A_S]));
-    if (MODE == kMean) {
-      value = (double(S_all) / double(g.n)) * two_eb;
-    } else {
-      const uint64_t ql = ld_dev(&p.s.acc[A_QLO]), qh = ld_dev(&p.s.acc[A_QHI]);
-      // M = n Q - S^2 (exact, non-negative)
-      const uint64_t n = g.n;
-      const uint64_t nql = n * ql;
-      const uint64_t nqh = n * qh + __umul64hi(n, ql);
-      const uint64_t a = uint64_t(S_all < 0 ? -S_all : S_all);
-      const uint64_t sl = a * a, sh = __umul64hi(a, a);
-      const uint64_t ml = nql - sl;
-      const uint64_t mh = nqh - sh - (nql < sl ? 1u : 0u);
-      const double m = u128_to_double(mh, ml);
-      value = ((m / double(n)) / double(n)) * (two_eb * two_eb);
-    }
+    double mean = 0.0, var = 0.0;
+    mean_variance(g.n, g.eb, S_all, ld_dev(&p.s.acc[A_QLO]), ld_dev(&p.s.acc[A_QHI]), mean, var);
+    value = MODE == kMean ? mean : var;
   }
   publish(p.s, p.res, 0, value);
 }
@@ -1337,10 +1421,10 @@ __global__ void __launch_bounds__(kThreads) k_add(AddParams p) {
     const uint64_t tile = uni64(s_ticket);
     if (tile >= ntiles) break;
     if (tid < 64) {
-      const uint64_t v = tile_offset(p.s.idx[0], tile);
+      const uint64_t v = tile_offset(p.s.idx[0], kWavesPerTile * tile);
       if (tid == 0) s_base_a = v;
     } else if (tid < 128) {
-      const uint64_t v = tile_offset(p.s.idx[1], tile);
+      const uint64_t v = tile_offset(p.s.idx[1], kWavesPerTile * tile);
       if (tid == 64) s_base_b = v;
     }
     uint32_t bad = 0;
@@ -1506,7 +1590,7 @@ __global__ void __launch_bounds__(kThreads) k_mul(MulParams p) {
     const uint64_t tile = uni64(s_ticket);
     if (tile >= ntiles) break;
     if (tid < 64) {
-      const uint64_t v = tile_offset(p.s.idx[0], tile);
+      const uint64_t v = tile_offset(p.s.idx[0], kWavesPerTile * tile);
       if (tid == 0) s_base = v;
     }
     uint32_t bad = 0;
