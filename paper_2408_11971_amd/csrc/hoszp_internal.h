@@ -48,6 +48,7 @@ constexpr uint32_t ST_CAPACITY = 1u << HOSZP_ERR_CAPACITY;
 struct Layout {
   uint64_t n, nb, nseg, ntiles, nwtiles;  // nwtiles: wave tiles
   uint32_t L, spb;  // block size, segments per block
+  uint32_t spb_log2;
   double eb;
   uint64_t off_w, off_o, off_s, off_p;
   uint64_t payload_bytes, total_bytes;
@@ -60,6 +61,7 @@ __host__ __device__ inline void place(Layout& g, uint64_t n, uint32_t L, double 
   g.n = n;
   g.L = L;
   g.spb = L / 32;
+  g.spb_log2 = L == 32 ? 0u : (L == 64 ? 1u : 2u);
   g.eb = eb;
   g.nb = (n + L - 1) / L;
   g.nseg = g.nb * g.spb;

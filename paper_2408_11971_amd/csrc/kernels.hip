@@ -513,8 +513,8 @@ __device__ __forceinline__ uint32_t widths_of_16(const uint8_t* c, const Layout&
                                                  uint32_t& bad) {
   if (seg0 >= g.nseg) return 0;
   const uint8_t* W = c + g.off_w;
-  const uint64_t b0 = seg0 / g.spb;               // first block
-  const uint64_t nbk = 16 / g.spb;                // blocks covered when whole
+  const uint64_t b0 = seg0 >> g.spb_log2;               // first block
+  const uint64_t nbk = 16u >> g.spb_log2;                // blocks covered when whole
   const uint64_t have = g.nb - b0 < nbk ? g.nb - b0 : nbk;
   uint32_t q[4] = {0, 0, 0, 0};
   if (have == nbk) {
@@ -947,11 +947,13 @@ __device__ __forceinline__ uint32_t weighted_popcount(uint32_t v) {
 // bit, slot i at bit 31 - i of `signs`):
 // E = sum_i (32 - i) x_i + sum_{i: s_i} (32 - i), all in 32-bit integers.
 // The same pass also yields D = the delta total (sum_i x_i + popcount(signs),
-// slot 0 of a block excluded).
+// slot 0 of a block excluded).  sum_i (32 - i) x_i is accumulated as the sum
+// of the running prefixes of x, one dependent add each, so no field value
+// outlives its own step.
 __device__ __forceinline__ int32_t mean_fast(const uint32_t* sp, uint32_t w, uint32_t signs,
                                              bool first_seg, int32_t& D) {
   const uint32_t rs = 32u - w;
-  int32_t acc = 0, tot = 0;
+  int32_t run = 0, acc = 0;
   uint32_t pbit = 0;
 #pragma unroll
   for (int j = 0; j < 32; ++j) {
@@ -959,11 +961,10 @@ __device__ __forceinline__ int32_t mean_fast(const uint32_t* sp, uint32_t w, uin
     pbit += w;
     int32_t x = m ^ (int32_t(signs << j) >> 31);
     if (j == 0 && first_seg) x = 0;
-    const int32_t c = j == 0 ? 32 : 32 - j;
-    acc += __mul24(x, c);
-    tot += x;
+    run += x;
+    acc += run;
   }
-  D = tot + int32_t(__popc(signs));
+  D = run + int32_t(__popc(signs));
   return acc + int32_t(weighted_popcount(signs));
 }
 
@@ -1013,17 +1014,19 @@ __device__ __forceinline__ int32_t prefix_fast(const uint32_t* sp, uint32_t w, u
 
 // Generic path: in-segment prefixes e_j of any segment (partial, or width up
 // to 32) with 64-bit/128-bit sums; keeps e_j when KEEP.
-template <bool KEEP>
+// (Rare: kept compact rather than fast, so it does not raise the register
+// count of the kernels' fast paths.)
+template <bool KEEP, typename KT = int64_t>
 __device__ __forceinline__ int64_t decode_generic(const uint32_t* sp, uint32_t sw, uint32_t w, uint32_t sub,
                                   uint32_t cnt, int64_t& E, unsigned __int128& E2,
-                                  int64_t* keep) {
+                                  KT* keep) {
   int64_t e = 0;
   E = 0;
   E2 = 0;
-#pragma unroll
-  for (int j = 0; j < 32; ++j) {
-    int64_t d = w ? seg_delta(sp, sw, w, j) : 0;
-    if (j == 0 && sub == 0) d = 0;  // slot 0 of a block is the outlier
+  const uint32_t ww = w ? w : 1u;  // with w = 0 every delta is 0 (fields read, then dropped)
+  auto step = [&](int j) {
+    int64_t d = seg_delta(sp, sw, ww, j);
+    if (w == 0 || (j == 0 && sub == 0)) d = 0;  // slot 0 of a block is the outlier
     const bool valid = uint32_t(j) < cnt;
     if (!valid) d = 0;
     e += d;
@@ -1032,7 +1035,16 @@ __device__ __forceinline__ int64_t decode_generic(const uint32_t* sp, uint32_t s
       const uint64_t a = uint64_t(e < 0 ? -e : e);
       E2 += (unsigned __int128)a * a;
     }
-    if (KEEP) keep[j] = e;
+  };
+  if constexpr (KEEP) {  // keep[] must stay in registers: fully unrolled
+#pragma unroll
+    for (int j = 0; j < 32; ++j) {
+      step(j);
+      keep[j] = KT(e);
+    }
+  } else {
+#pragma unroll 2
+    for (int j = 0; j < 32; ++j) step(j);
   }
   return e;
 }
@@ -1045,7 +1057,7 @@ __device__ __forceinline__ uint32_t stage_tile(const uint8_t* c, const Layout& g
                                                const uint64_t* s_base, uint32_t& w,
                                                uint32_t& tile_words, uint32_t& bad) {
   const uint64_t seg = tile * kTileSegs + threadIdx.x;
-  w = seg < g.nseg ? c[g.off_w + seg / g.spb] : 0u;
+  w = seg < g.nseg ? c[g.off_w + (seg >> g.spb_log2)] : 0u;
   if (w > 32) {
     bad |= ST_FORMAT;
     w = 0;
@@ -1083,7 +1095,7 @@ __device__ __forceinline__ void meta_a(const Layout& g, const uint8_t* W, const 
   const int lane = threadIdx.x & 63;
   const uint64_t seg = wt * kWaveSegs + lane;
   const bool active = wt < nwt && seg < g.nseg;
-  const uint64_t blk = seg / g.spb;
+  const uint64_t blk = (seg >> g.spb_log2);
   m.w = active ? W[blk] : 0u;
   m.outlier = active ? O[blk] : 0;
   const uint64_t chunk = wt / kChunkTiles;
@@ -1102,8 +1114,8 @@ __device__ __forceinline__ void meta_b(const Layout& g, const uint32_t* S, const
     w = 0;
   }
   const uint64_t seg = wt * kWaveSegs + lane;
-  const uint64_t blk = seg / g.spb;
-  const uint32_t sub = uint32_t(seg % g.spb);
+  const uint64_t blk = (seg >> g.spb_log2);
+  const uint32_t sub = uint32_t(seg & (g.spb - 1));
   uint64_t blen = 0;
   const uint32_t cnt = (wt < nwt && seg < g.nseg) ? seg_count(g, blk, sub, blen) : 0u;
   uint32_t x = w;  // inclusive scan of the widths over the wave
@@ -1136,7 +1148,8 @@ __device__ __forceinline__ void meta_b(const Layout& g, const uint32_t* S, const
 // one tile ahead, so memory latency overlaps the current tile's arithmetic.
 template <int MODE>
 __global__ void __launch_bounds__(kThreads) k_decode(DecodeParams p) {
-  __shared__ uint32_t s_pay[kThreads / 64][kWaveWords + 2];
+  // per-wave payload staging, reused by decompression to transpose its output
+  __shared__ __align__(16) uint32_t s_pay[kThreads / 64][kWaveWords + 4];
   __shared__ uint32_t s_flag;
   __shared__ int64_t s_rs[kThreads / 64];
   __shared__ uint64_t s_rl[kThreads / 64], s_rh[kThreads / 64];
@@ -1190,8 +1203,8 @@ __global__ void __launch_bounds__(kThreads) k_decode(DecodeParams p) {
 
     const uint64_t seg = wt * kWaveSegs + lane;
     const bool active = seg < g.nseg;
-    const uint64_t blk = seg / g.spb;
-    const uint32_t sub = uint32_t(seg % g.spb);
+    const uint64_t blk = (seg >> g.spb_log2);
+    const uint32_t sub = uint32_t(seg & (g.spb - 1));
     uint64_t blen = 0;
     const uint32_t cnt = active ? seg_count(g, blk, sub, blen) : 0u;
 
@@ -1201,7 +1214,8 @@ __global__ void __launch_bounds__(kThreads) k_decode(DecodeParams p) {
     int64_t D = 0, E = 0;
     uint64_t E2 = 0;
     unsigned __int128 E2w = 0;
-    int64_t keep[MODE == kDecompress ? 32 : 1];
+    // decompression keeps the in-segment prefixes modulo 2^32: every bin of a
+    // valid stream is an int32, so carry + prefix wraps to the exact bin
     int32_t keep32[MODE == kDecompress ? 32 : 1];
     if (fast) {
       if (w == 0) {
@@ -1225,7 +1239,7 @@ __global__ void __launch_bounds__(kThreads) k_decode(DecodeParams p) {
         D = prefix_fast(sp, w, sw, sub == 0, keep32);
       }
     } else if (cnt > 0) {
-      D = decode_generic<MODE == kDecompress>(sp, sw, w, sub, cnt, E, E2w, keep);
+      D = decode_generic<MODE == kDecompress, int32_t>(sp, sw, w, sub, cnt, E, E2w, keep32);
     }
     const int64_t carry = int64_t(outlier) + block_excl(D, g.spb);
     // every bin must be a valid int32 bin (slot 0 is the outlier itself)
@@ -1239,24 +1253,40 @@ __global__ void __launch_bounds__(kThreads) k_decode(DecodeParams p) {
     }
 
     if (MODE == kDecompress) {
+      // Bins -> floats, written to LDS in segment order with float4 chunks
+      // XOR-swizzled by lane (conflict-free), then stored with consecutive
+      // lanes on consecutive 16-byte chunks.  The payload words are no longer
+      // needed: the wave has finished reading them.
+      __builtin_amdgcn_wave_barrier();
+      float* fl = reinterpret_cast<float*>(wp);
       if (cnt > 0) {
-        const uint64_t first = blk * g.L + uint64_t(32) * sub;
-        if (fast) {  // bins are carry + e_j (mod 2^32), always int32 here
-          float4* dst = reinterpret_cast<float4*>(p.x + first);
-          const int32_t c32 = int32_t(carry);
+        const uint32_t c32 = uint32_t(carry);
+        auto val = [&](int j) { return float(double(int32_t(c32 + uint32_t(keep32[j]))) * two_eb); };
 #pragma unroll
-          for (int k = 0; k < 8; ++k) {
-            float4 t;
-            t.x = float(double(c32 + keep32[4 * k + 0]) * two_eb);
-            t.y = float(double(c32 + keep32[4 * k + 1]) * two_eb);
-            t.z = float(double(c32 + keep32[4 * k + 2]) * two_eb);
-            t.w = float(double(c32 + keep32[4 * k + 3]) * two_eb);
-            dst[k] = t;
-          }
-        } else {
+        for (int k = 0; k < 8; ++k) {
+          float4 t;
+          t.x = val(4 * k + 0);
+          t.y = val(4 * k + 1);
+          t.z = val(4 * k + 2);
+          t.w = val(4 * k + 3);
+          *reinterpret_cast<float4*>(&fl[lane * 32 + 4 * (k ^ (lane & 7))]) = t;
+          __builtin_amdgcn_sched_barrier(0);  // convert chunk by chunk (register pressure)
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+      const uint64_t e0 = wt * (uint64_t(kWaveSegs) * 32);
+      const uint64_t left = g.n - e0;
+      const uint32_t valid = uint32_t(left < uint64_t(kWaveSegs) * 32 ? left : uint64_t(kWaveSegs) * 32);
 #pragma unroll
-          for (int j = 0; j < 32; ++j)
-            if (uint32_t(j) < cnt) p.x[first + j] = float(double(carry + keep[j]) * two_eb);
+      for (int k = 0; k < 8; ++k) {
+        const uint32_t q = uint32_t(lane) + 64u * k;  // float4 chunk of the wave tile
+        const uint32_t row = q >> 3, ch = q & 7u;
+        const float4 v = *reinterpret_cast<const float4*>(&fl[row * 32 + 4 * (ch ^ (row & 7u))]);
+        if (4 * q + 4 <= valid) {
+          *reinterpret_cast<float4*>(p.x + e0 + 4 * q) = v;
+        } else if (4 * q < valid) {
+          const float vv[4] = {v.x, v.y, v.z, v.w};
+          for (uint32_t t = 0; 4 * q + t < valid; ++t) p.x[e0 + 4 * q + t] = vv[t];
         }
       }
     } else if (cnt > 0) {
@@ -1356,12 +1386,12 @@ __global__ void __launch_bounds__(kThreads) k_negate(NegateParams p) {
         const uint64_t b0 = o + 4 * q;
         if (b0 >= s_end) continue;
         const uint64_t seg = (b0 - g.off_s) / 4;
-        const uint64_t blk = seg / g.spb;
+        const uint64_t blk = (seg >> g.spb_log2);
         if (p.c[g.off_w + blk] == 0) continue;  // constant block: no signs
         uint32_t cnt = 32;
         if (blk == g.nb - 1) {
           uint64_t blen;
-          cnt = seg_count(g, blk, uint32_t(seg % g.spb), blen);
+          cnt = seg_count(g, blk, uint32_t(seg & (g.spb - 1)), blen);
         }
         if (cnt == 0) continue;
         const uint32_t be = cnt == 32 ? 0xffffffffu : ~(0xffffffffu >> cnt);
@@ -1433,8 +1463,8 @@ __global__ void __launch_bounds__(kThreads) k_add(AddParams p) {
     const uint32_t off_b = stage_tile(p.b, gb, tile, s_b, s_tmp, &s_base_b, wb, tw_b, bad);
     const uint64_t seg = tile * kTileSegs + tid;
     const bool active = seg < g.nseg;
-    const uint64_t blk = seg / g.spb;
-    const uint32_t sub = uint32_t(seg % g.spb);
+    const uint64_t blk = (seg >> g.spb_log2);
+    const uint32_t sub = uint32_t(seg & (g.spb - 1));
     uint64_t blen = 0;
     const uint32_t cnt = active ? seg_count(g, blk, sub, blen) : 0u;
     const int64_t oa = active ? Oa[blk] : 0, ob = active ? Ob[blk] : 0;
@@ -1598,8 +1628,8 @@ __global__ void __launch_bounds__(kThreads) k_mul(MulParams p) {
     const uint32_t off = stage_tile(p.c, g, tile, s_pay, s_tmp, &s_base, w, tile_words, bad);
     const uint64_t seg = tile * kTileSegs + tid;
     const bool active = seg < g.nseg;
-    const uint64_t blk = seg / g.spb;
-    const uint32_t sub = uint32_t(seg % g.spb);
+    const uint64_t blk = (seg >> g.spb_log2);
+    const uint32_t sub = uint32_t(seg & (g.spb - 1));
     uint64_t blen = 0;
     const uint32_t cnt = active ? seg_count(g, blk, sub, blen) : 0u;
     const int32_t outlier = active ? O[blk] : 0;
