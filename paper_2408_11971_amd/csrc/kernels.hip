@@ -28,6 +28,9 @@ constexpr uint64_t kLbAgg = 1, kLbInc = 2;
 constexpr uint64_t kLbValMask = (uint64_t(1) << 34) - 1;
 constexpr uint32_t kNone = 0xffffffffu;
 constexpr uint32_t kEpochLimit = 1u << 28;
+// Workgroup size (= segments per look-back tile) of single-field compression:
+// larger tiles halve the serial look-back steps.
+constexpr int kCompressThreads = 1024;
   // look-back epochs are 28-bit, never 0
 
 enum { kMean = 0, kVariance = 1, kDecompress = 2 };
@@ -164,6 +167,7 @@ __device__ __forceinline__ void write_header(uint8_t* out, const Layout& g, uint
 
 // Exclusive scan of one value per thread over the workgroup, plus the total.
 // Contains barriers: call from workgroup-uniform control flow.
+template <int NT = kThreads>
 __device__ __forceinline__ uint32_t wg_scan(uint32_t v, uint32_t& total, uint32_t* tmp) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t x = v;
@@ -176,7 +180,7 @@ __device__ __forceinline__ uint32_t wg_scan(uint32_t v, uint32_t& total, uint32_
   __syncthreads();
   uint32_t before = 0, all = 0;
 #pragma unroll
-  for (int w = 0; w < kThreads / 64; ++w) {
+  for (int w = 0; w < NT / 64; ++w) {
     const uint32_t t = tmp[w];
     before += (w < wave) ? t : 0u;
     all += t;
@@ -214,10 +218,11 @@ __device__ __forceinline__ uint64_t lb_word(uint32_t epoch, uint64_t flag, uint6
   return (uint64_t(epoch) << 36) | (flag << 34) | (v & kLbValMask);
 }
 
+template <int NT = kThreads>
 struct LbShared {
-  uint32_t first_inc[kThreads / 64];
-  uint32_t first_wait[kThreads / 64];
-  uint64_t part[kThreads / 64];
+  uint32_t first_inc[NT / 64];
+  uint32_t first_wait[NT / 64];
+  uint64_t part[NT / 64];
   uint64_t near_sum;
   uint32_t near_found;
 };
@@ -239,8 +244,9 @@ __device__ __forceinline__ void lb_publish(uint64_t* st, uint64_t tile, uint64_t
 }
 
 // Contains barriers (except for tile 0, which returns at once).
+template <int NT = kThreads>
 __device__ __forceinline__ uint64_t lb_wait(uint64_t* st, uint64_t tile, uint64_t agg,
-                                            uint32_t epoch, LbShared& sh) {
+                                            uint32_t epoch, LbShared<NT>& sh) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (tile == 0) return 0;
   if (wave == 0) {
@@ -300,7 +306,7 @@ __device__ __forceinline__ uint64_t lb_wait(uint64_t* st, uint64_t tile, uint64_
       fi = kNone;
       fw = kNone;
 #pragma unroll
-      for (int k = 0; k < kThreads / 64; ++k) {
+      for (int k = 0; k < NT / 64; ++k) {
         fi = min(fi, sh.first_inc[k]);
         fw = min(fw, sh.first_wait[k]);
       }
@@ -316,21 +322,22 @@ __device__ __forceinline__ uint64_t lb_wait(uint64_t* st, uint64_t tile, uint64_
       __syncthreads();
       uint64_t total = 0;
 #pragma unroll
-      for (int k = 0; k < kThreads / 64; ++k) total += sh.part[k];
+      for (int k = 0; k < NT / 64; ++k) total += sh.part[k];
       __syncthreads();
       excl += uni64(total);
       if (fi != kNone) break;
-      base -= kThreads;
+      base -= NT;
     }
   }
   if (tid == 0) st_dev(&st[tile], lb_word(epoch, kLbInc, excl + agg));
   return excl;
 }
 
+template <int NT = kThreads>
 __device__ __forceinline__ uint64_t wg_lookback(uint64_t* st, uint64_t tile, uint64_t agg,
-                                                uint32_t epoch, LbShared& sh) {
+                                                uint32_t epoch, LbShared<NT>& sh) {
   lb_publish(st, tile, agg, epoch);
-  return lb_wait(st, tile, agg, epoch, sh);
+  return lb_wait<NT>(st, tile, agg, epoch, sh);
 }
 
 // Payload word offset of wave tile `tile` of a stream from its width
@@ -444,6 +451,7 @@ __device__ __forceinline__ double u128_to_double(uint64_t hi, uint64_t lo) {
 
 // Sum over the workgroup of an int64 and an unsigned 128-bit value (hi:lo);
 // the result is valid in thread 0.  Contains barriers.
+template <int NT = kThreads>
 __device__ __forceinline__ void wg_sum_s_q(int64_t& s, uint64_t& qlo, uint64_t& qhi, int64_t* ts, uint64_t* tl,
                            uint64_t* th) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -466,7 +474,7 @@ __device__ __forceinline__ void wg_sum_s_q(int64_t& s, uint64_t& qlo, uint64_t& 
     s = 0;
     qlo = 0;
     qhi = 0;
-    for (int w = 0; w < kThreads / 64; ++w) {
+    for (int w = 0; w < NT / 64; ++w) {
       s += ts[w];
       const uint64_t nl = qlo + tl[w];
       qhi = qhi + th[w] + (nl < qlo ? 1u : 0u);
@@ -670,12 +678,13 @@ __device__ __forceinline__ void quantize_segment(const float* v, uint32_t cnt, b
 }
 
 // LDS of one compress workgroup.
+template <int NT = kThreads>
 struct CompressShared {
-  uint32_t pay[kTileWords + 2];
-  uint32_t tmp[kThreads / 64];
-  LbShared lb;
-  int64_t rs[kThreads / 64];
-  uint64_t rl[kThreads / 64], rh[kThreads / 64];
+  uint32_t pay[NT * 32 + 2];
+  uint32_t tmp[NT / 64];
+  LbShared<NT> lb;
+  int64_t rs[NT / 64];
+  uint64_t rl[NT / 64], rh[NT / 64];
   uint64_t ticket;
   uint32_t flag;
 };
@@ -687,14 +696,15 @@ struct CompressShared {
 // `bad`; with STATS the tile's valid bins are added to `sums`.  Thread 0
 // takes the workgroup's next ticket from `ticket` into `next`.  Contains
 // barriers.
-template <int SPB, bool STATS>
+template <int SPB, bool STATS, int NT = kThreads>
 __device__ __forceinline__ uint64_t compress_tile(const float* x, uint8_t* out, const Layout& g, double eb,
                                   double inv2e, uint64_t tile, uint64_t* st, uint32_t epoch,
-                                  CompressShared& sh, uint32_t& bad, BinSums& sums,
+                                  CompressShared<NT>& sh, uint32_t& bad, BinSums& sums,
                                   uint32_t* ticket, uint32_t& next) {
   constexpr uint32_t L = SPB * 32;
   const int tid = threadIdx.x;
-  const uint64_t seg = tile * kTileSegs + tid;
+  const uint64_t seg = tile * NT + tid;
+  const uint64_t ntiles = (g.nseg + NT - 1) / NT;
   const bool active = seg < g.nseg;
   const uint64_t blk = seg / SPB;
   const uint32_t sub = uint32_t(seg % SPB);
@@ -738,7 +748,7 @@ __device__ __forceinline__ uint64_t compress_tile(const float* x, uint8_t* out, 
   const uint32_t w = bitlen32(mx);
 
   uint32_t tile_words;
-  const uint32_t off = wg_scan(w, tile_words, sh.tmp);
+  const uint32_t off = wg_scan<NT>(w, tile_words, sh.tmp);
   // Publish the tile's payload size as soon as it is known, then do all work
   // that does not need the tile's offset (packing into LDS, the width,
   // outlier and sign sections) before waiting on the predecessors.
@@ -751,23 +761,24 @@ __device__ __forceinline__ uint64_t compress_tile(const float* x, uint8_t* out, 
     }
     reinterpret_cast<uint32_t*>(out + g.off_s)[seg] = bswap32(sgn);
   }
-  const uint64_t base = lb_wait(st, tile, tile_words, epoch, sh.lb);
+  const uint64_t base = lb_wait<NT>(st, tile, tile_words, epoch, sh.lb);
   // The next tile is requested now: its ticket is held only while this tile
   // stores, never while this tile waits on its predecessors.
   if (tid == 0) next = atomicAdd(ticket, 1u);
   __syncthreads();
   uint32_t* P = reinterpret_cast<uint32_t*>(out + g.off_p) + base;
-  for (uint32_t k = tid; k < tile_words; k += kThreads) P[k] = bswap32(sh.pay[k]);
-  if (tid == 0 && tile == g.ntiles - 1) write_header(out, g, 4 * (base + tile_words));
+  for (uint32_t k = tid; k < tile_words; k += NT) P[k] = bswap32(sh.pay[k]);
+  if (tid == 0 && tile == ntiles - 1) write_header(out, g, 4 * (base + tile_words));
   __syncthreads();
   return base + tile_words;
 }
 
-template <int SPB>
-__global__ void __launch_bounds__(kThreads) k_compress(CompressParams p) {
-  __shared__ CompressShared sh;
+template <int SPB, int NT>
+__global__ void __launch_bounds__(NT) k_compress(CompressParams p) {
+  __shared__ CompressShared<NT> sh;
   const int tid = threadIdx.x;
   const Layout& g = p.g;
+  const uint64_t ntiles = (g.nseg + NT - 1) / NT;
   uint32_t bad = 0, next = 0;
   BinSums none;
   if (tid == 0) next = atomicAdd(&p.s.ctrl[C_TICKET], 1u);
@@ -775,11 +786,11 @@ __global__ void __launch_bounds__(kThreads) k_compress(CompressParams p) {
     if (tid == 0) sh.ticket = next;
     __syncthreads();
     const uint64_t tile = uni64(sh.ticket);
-    if (tile >= g.ntiles) break;
+    if (tile >= ntiles) break;
     const uint64_t words =
-        compress_tile<SPB, false>(p.x, p.out, g, p.eb, p.inv2e, tile, p.s.st_out, p.epoch, sh,
+        compress_tile<SPB, false, NT>(p.x, p.out, g, p.eb, p.inv2e, tile, p.s.st_out, p.epoch, sh,
                                   bad, none, &p.s.ctrl[C_TICKET], next);
-    if (tid == 0 && tile == g.ntiles - 1) st_dev(&p.s.acc[A_OUT], g.off_p + 4 * words);
+    if (tid == 0 && tile == ntiles - 1) st_dev(&p.s.acc[A_OUT], g.off_p + 4 * words);
   }
   latch(p.s, bad);
   if (finish_arrive(&p.s.ctrl[C_DONE], &sh.flag))
@@ -833,7 +844,7 @@ struct BatchParams {
 // the field's result record and clears the accumulators.  Contains barriers.
 __device__ __forceinline__ void batch_flush(const BatchParams& p, uint32_t f, const Layout& g,
                                             BinSums& sums, uint32_t bad, uint32_t count,
-                                            CompressShared& sh) {
+                                            CompressShared<>& sh) {
   const int tid = threadIdx.x;
   wg_sum_s_q(sums.s, sums.ql, sums.qh, sh.rs, sh.rl, sh.rh);
   bad = uint32_t(__ballot(bad & ST_RANGE) ? ST_RANGE : 0u) |
@@ -868,7 +879,7 @@ __device__ __forceinline__ void batch_flush(const BatchParams& p, uint32_t f, co
 }
 
 __global__ void __launch_bounds__(kThreads) k_batch(BatchParams p) {
-  __shared__ CompressShared sh;
+  __shared__ CompressShared<> sh;
   const int tid = threadIdx.x;
   const uint32_t epoch = uni32(ld_dev32(&p.ctrl[B_EPOCH]));
   uint32_t next = 0;
@@ -1428,7 +1439,7 @@ __global__ void __launch_bounds__(kThreads) k_add(AddParams p) {
   __shared__ uint32_t s_tmp[kThreads / 64];
   __shared__ uint64_t s_ticket, s_base_a, s_base_b;
   __shared__ uint32_t s_flag;
-  __shared__ LbShared s_lb;
+  __shared__ LbShared<> s_lb;
   const int tid = threadIdx.x;
   Layout g, gb;
   uint32_t err = read_header(p.a, p.a_bytes, g);
@@ -1603,7 +1614,7 @@ __global__ void __launch_bounds__(kThreads) k_mul(MulParams p) {
   __shared__ uint32_t s_tmp[kThreads / 64];
   __shared__ uint64_t s_ticket, s_base;
   __shared__ uint32_t s_flag;
-  __shared__ LbShared s_lb;
+  __shared__ LbShared<> s_lb;
   const int tid = threadIdx.x;
   Layout g;
   uint32_t err = read_header(p.c, p.c_bytes, g);
@@ -1812,11 +1823,12 @@ hipError_t launch_compress(const Scratch& s, const Grids& gr, const float* x, co
                            double inv2e, uint8_t* out, uint32_t epoch, hoszp_result* res,
                            hipStream_t st) {
   CompressParams p{x, out, g, g.eb, inv2e, s, epoch, res};
-  const uint64_t grid = g.ntiles < uint64_t(gr.compress) ? g.ntiles : uint64_t(gr.compress);
+  const uint64_t ntiles = (g.nseg + kCompressThreads - 1) / kCompressThreads;
+  const uint64_t grid = ntiles < uint64_t(gr.compress) ? ntiles : uint64_t(gr.compress);
   switch (g.L) {
-    case 32: hipLaunchKernelGGL(k_compress<1>, dim3(uint32_t(grid)), dim3(kThreads), 0, st, p); break;
-    case 64: hipLaunchKernelGGL(k_compress<2>, dim3(uint32_t(grid)), dim3(kThreads), 0, st, p); break;
-    case 128: hipLaunchKernelGGL(k_compress<4>, dim3(uint32_t(grid)), dim3(kThreads), 0, st, p); break;
+    case 32: hipLaunchKernelGGL((k_compress<1, kCompressThreads>), dim3(uint32_t(grid)), dim3(kCompressThreads), 0, st, p); break;
+    case 64: hipLaunchKernelGGL((k_compress<2, kCompressThreads>), dim3(uint32_t(grid)), dim3(kCompressThreads), 0, st, p); break;
+    case 128: hipLaunchKernelGGL((k_compress<4, kCompressThreads>), dim3(uint32_t(grid)), dim3(kCompressThreads), 0, st, p); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1910,7 +1922,7 @@ int batch_max_grid(int num_cus) {
 
 hipError_t query_grids(Grids& gr, int num_cus) {
   int c = 0, d = 0, a = 0, m = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&c, k_compress<1>, kThreads, 0);
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&c, k_compress<1, kCompressThreads>, kCompressThreads, 0);
   if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&d, k_decode<kVariance>, kThreads, 0);
   if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_add, kThreads, 0);
   if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&m, k_mul, kThreads, 0);
