@@ -607,7 +607,7 @@ int hoszp_batch_create(hoszp_ctx* ctx, const hoszp_field* fields, uint64_t count
     hz::place(g, fields[i].n, blocks[i], fields[i].eb);
     hf[i] = hz::BatchField{fields[i].d_x, static_cast<uint8_t*>(fields[i].d_out), fields[i].n,
                            fields[i].eb, 1.0 / (2.0 * fields[i].eb), tiles, blocks[i], 0};
-    tiles += g.ntiles;
+    tiles += hz::batch_tiles(g);
     raw += 4 * fields[i].n;
   }
   delete[] blocks;
@@ -642,7 +642,7 @@ int hoszp_batch_create(hoszp_ctx* ctx, const hoszp_field* fields, uint64_t count
       for (uint64_t i = 0; i < count; ++i) {
         hz::Layout g;
         hz::place(g, hf[i].n, hf[i].block, hf[i].eb);
-        for (uint64_t k = 0; k < g.ntiles; ++k) tf[t++] = uint32_t(i);
+        for (uint64_t k = 0; k < hz::batch_tiles(g); ++k) tf[t++] = uint32_t(i);
       }
       const uint32_t epoch1 = 1;
       if (hipMemsetAsync(b->d_mem, 0, b->device_bytes, st) != hipSuccess ||

@@ -132,6 +132,11 @@ struct BatchDev {
   hoszp_field_result* res;
 };
 constexpr int kBatchAccWords = 8;  // accumulator words per field
+// Workgroup size of the batched compress = segments per work-list tile.
+constexpr int kBatchThreads = 1024;
+inline __host__ __device__ uint64_t batch_tiles(const Layout& g) {
+  return (g.nseg + kBatchThreads - 1) / kBatchThreads;
+}
 
 // Occupancy-derived persistent grid sizes, filled at context creation.
 struct Grids {

@@ -844,9 +844,9 @@ struct BatchParams {
 // the field's result record and clears the accumulators.  Contains barriers.
 __device__ __forceinline__ void batch_flush(const BatchParams& p, uint32_t f, const Layout& g,
                                             BinSums& sums, uint32_t bad, uint32_t count,
-                                            CompressShared<>& sh) {
+                                            CompressShared<kBatchThreads>& sh) {
   const int tid = threadIdx.x;
-  wg_sum_s_q(sums.s, sums.ql, sums.qh, sh.rs, sh.rl, sh.rh);
+  wg_sum_s_q<kBatchThreads>(sums.s, sums.ql, sums.qh, sh.rs, sh.rl, sh.rh);
   bad = uint32_t(__ballot(bad & ST_RANGE) ? ST_RANGE : 0u) |
         uint32_t(__ballot(bad & ST_NONFINITE) ? ST_NONFINITE : 0u);
   uint64_t* acc = p.facc + uint64_t(f) * F_WORDS;
@@ -859,7 +859,7 @@ __device__ __forceinline__ void batch_flush(const BatchParams& p, uint32_t f, co
     atomicAdd(reinterpret_cast<unsigned long long*>(&acc[F_QHI]),
               (unsigned long long)(sums.qh + carry));
   }
-  if (finish_arrive_n(reinterpret_cast<uint32_t*>(&acc[F_DONE]), count, uint32_t(g.ntiles),
+  if (finish_arrive_n(reinterpret_cast<uint32_t*>(&acc[F_DONE]), count, uint32_t(batch_tiles(g)),
                       &sh.flag) &&
       tid == 0) {
     const uint32_t status = uint32_t(ld_dev(&acc[F_STATUS]));
@@ -878,8 +878,8 @@ __device__ __forceinline__ void batch_flush(const BatchParams& p, uint32_t f, co
   sums = BinSums();
 }
 
-__global__ void __launch_bounds__(kThreads) k_batch(BatchParams p) {
-  __shared__ CompressShared<> sh;
+__global__ void __launch_bounds__(kBatchThreads) k_batch(BatchParams p) {
+  __shared__ CompressShared<kBatchThreads> sh;
   const int tid = threadIdx.x;
   const uint32_t epoch = uni32(ld_dev32(&p.ctrl[B_EPOCH]));
   uint32_t next = 0;
@@ -909,26 +909,26 @@ __global__ void __launch_bounds__(kThreads) k_batch(BatchParams p) {
     uint64_t words = 0;
     switch (g.spb) {
       case 1:
-        words = compress_tile<1, true>(fd.x, fd.out, g, fd.eb, fd.inv2e, tile, p.st + fd.tile0,
+        words = compress_tile<1, true, kBatchThreads>(fd.x, fd.out, g, fd.eb, fd.inv2e, tile, p.st + fd.tile0,
                                        epoch, sh, bad, sums, &p.ctrl[B_TICKET], next);
         break;
       case 2:
-        words = compress_tile<2, true>(fd.x, fd.out, g, fd.eb, fd.inv2e, tile, p.st + fd.tile0,
+        words = compress_tile<2, true, kBatchThreads>(fd.x, fd.out, g, fd.eb, fd.inv2e, tile, p.st + fd.tile0,
                                        epoch, sh, bad, sums, &p.ctrl[B_TICKET], next);
         break;
       default:
-        words = compress_tile<4, true>(fd.x, fd.out, g, fd.eb, fd.inv2e, tile, p.st + fd.tile0,
+        words = compress_tile<4, true, kBatchThreads>(fd.x, fd.out, g, fd.eb, fd.inv2e, tile, p.st + fd.tile0,
                                        epoch, sh, bad, sums, &p.ctrl[B_TICKET], next);
         break;
     }
     ++count;
-    if (tid == 0 && tile == g.ntiles - 1)
+    if (tid == 0 && tile == batch_tiles(g) - 1)
       st_dev(&p.facc[uint64_t(f) * F_WORDS + F_OUT], g.off_p + 4 * words);
   }
   if (finish_arrive_n(&p.ctrl[B_DONE], 1u, gridDim.x, &sh.flag)) {
     const bool wrap = epoch + 1 >= kEpochLimit;  // epochs wrap: clear every status word
     if (wrap)
-      for (uint64_t k = tid; k < p.total_tiles; k += kThreads) p.st[k] = 0;
+      for (uint64_t k = tid; k < p.total_tiles; k += kBatchThreads) p.st[k] = 0;
     if (tid == 0) {
       p.ctrl[B_TICKET] = 0;
       p.ctrl[B_DONE] = 0;
@@ -1909,13 +1909,13 @@ hipError_t launch_zero64(uint64_t* p, uint64_t n, hipStream_t st) {
 
 hipError_t launch_batch(const BatchDev& b, int grid, hipStream_t st) {
   BatchParams p{b.fields, b.tile_field, b.total_tiles, b.st, b.ctrl, b.facc, b.res};
-  hipLaunchKernelGGL(k_batch, dim3(uint32_t(grid)), dim3(kThreads), 0, st, p);
+  hipLaunchKernelGGL(k_batch, dim3(uint32_t(grid)), dim3(kBatchThreads), 0, st, p);
   return hipGetLastError();
 }
 
 int batch_max_grid(int num_cus) {
   int occ = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch, kThreads, 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch, kBatchThreads, 0) != hipSuccess)
     return num_cus;
   return num_cus * (occ < 1 ? 1 : occ);
 }
