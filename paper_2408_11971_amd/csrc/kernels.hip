@@ -31,6 +31,7 @@ constexpr uint32_t kEpochLimit = 1u << 28;
 // Workgroup size (= segments per look-back tile) of single-field compression:
 // larger tiles halve the serial look-back steps.
 constexpr int kCompressThreads = 1024;
+constexpr int kMulThreads = 1024;
   // look-back epochs are 28-bit, never 0
 
 enum { kMean = 0, kVariance = 1, kDecompress = 2 };
@@ -405,11 +406,12 @@ __device__ __forceinline__ bool bins_surely_in_range(int64_t outlier, uint64_t b
 // Stage payload words [base, base + words) of a stream into LDS (sp[1..]) with
 // a zero guard word on each side.  Returns false when the range leaves the
 // payload section (nothing is read then).
+template <int NT = kThreads>
 __device__ __forceinline__ bool stage_payload(uint32_t* sp, const uint32_t* P, uint64_t base, uint32_t words,
                               uint64_t payload_words) {
   const bool fits = base + words <= payload_words;
   if (fits)
-    for (uint32_t k = threadIdx.x; k < words; k += kThreads) sp[1 + k] = bswap32(P[base + k]);
+    for (uint32_t k = threadIdx.x; k < words; k += NT) sp[1 + k] = bswap32(P[base + k]);
   if (threadIdx.x == 0) {
     sp[0] = 0;
     sp[1 + words] = 0;
@@ -1063,20 +1065,21 @@ __device__ __forceinline__ int64_t decode_generic(const uint32_t* sp, uint32_t s
 // Load the widths of a tile, scan them, and stage its payload words in LDS.
 // *s_base holds the tile's payload word offset once the scan's barriers have
 // passed.  Returns the segment's word offset in the tile.
+template <int NT = kThreads>
 __device__ __forceinline__ uint32_t stage_tile(const uint8_t* c, const Layout& g, uint64_t tile,
                                                uint32_t* s_pay, uint32_t* s_tmp,
                                                const uint64_t* s_base, uint32_t& w,
                                                uint32_t& tile_words, uint32_t& bad) {
-  const uint64_t seg = tile * kTileSegs + threadIdx.x;
+  const uint64_t seg = tile * NT + threadIdx.x;
   w = seg < g.nseg ? c[g.off_w + (seg >> g.spb_log2)] : 0u;
   if (w > 32) {
     bad |= ST_FORMAT;
     w = 0;
   }
-  const uint32_t off = wg_scan(w, tile_words, s_tmp);  // its barriers publish *s_base
+  const uint32_t off = wg_scan<NT>(w, tile_words, s_tmp);  // its barriers publish *s_base
   const uint64_t base = uni64(*s_base);
   const uint32_t* P = reinterpret_cast<const uint32_t*>(c + g.off_p);
-  if (!stage_payload(s_pay, P, base, tile_words, g.payload_bytes / 4)) bad |= ST_FORMAT;
+  if (!stage_payload<NT>(s_pay, P, base, tile_words, g.payload_bytes / 4)) bad |= ST_FORMAT;
   return off;
 }
 
@@ -1609,18 +1612,23 @@ __device__ __forceinline__ int32_t scaled_bin(int64_t q, const MulScalar& k, uin
   return int32_t(r);
 }
 
-__global__ void __launch_bounds__(kThreads) k_mul(MulParams p) {
-  __shared__ uint32_t s_pay[kTileWords + 2];
-  __shared__ uint32_t s_tmp[kThreads / 64];
+// Scalar multiplication, one tile of NT segments per workgroup: decode the
+// bins (in-segment prefixes kept modulo 2^32: every bin of a valid stream is
+// an int32, so carry + prefix wraps to the exact bin), scale them, and
+// re-encode with the output look-back.
+template <int NT>
+__global__ void __launch_bounds__(NT) k_mul(MulParams p) {
+  __shared__ uint32_t s_pay[NT * 32 + 2];
+  __shared__ uint32_t s_tmp[NT / 64];
   __shared__ uint64_t s_ticket, s_base;
   __shared__ uint32_t s_flag;
-  __shared__ LbShared<> s_lb;
+  __shared__ LbShared<NT> s_lb;
   const int tid = threadIdx.x;
   Layout g;
   uint32_t err = read_header(p.c, p.c_bytes, g);
   if (!err && p.out_cap < bound_bytes(g.n, g.L)) err = ST_CAPACITY;
   if (tid == 0 && blockIdx.x == 0) latch(p.s, err);
-  const uint64_t ntiles = err ? 0 : g.ntiles;
+  const uint64_t ntiles = err ? 0 : (g.nseg + NT - 1) / NT;
   const uint32_t* S = reinterpret_cast<const uint32_t*>(p.c + g.off_s);
   const int32_t* O = reinterpret_cast<const int32_t*>(p.c + g.off_o);
   uint32_t next = 0;
@@ -1631,13 +1639,13 @@ __global__ void __launch_bounds__(kThreads) k_mul(MulParams p) {
     const uint64_t tile = uni64(s_ticket);
     if (tile >= ntiles) break;
     if (tid < 64) {
-      const uint64_t v = tile_offset(p.s.idx[0], kWavesPerTile * tile);
+      const uint64_t v = tile_offset(p.s.idx[0], (NT / kWaveSegs) * tile);
       if (tid == 0) s_base = v;
     }
     uint32_t bad = 0;
     uint32_t w, tile_words;
-    const uint32_t off = stage_tile(p.c, g, tile, s_pay, s_tmp, &s_base, w, tile_words, bad);
-    const uint64_t seg = tile * kTileSegs + tid;
+    const uint32_t off = stage_tile<NT>(p.c, g, tile, s_pay, s_tmp, &s_base, w, tile_words, bad);
+    const uint64_t seg = tile * NT + tid;
     const bool active = seg < g.nseg;
     const uint64_t blk = (seg >> g.spb_log2);
     const uint32_t sub = uint32_t(seg & (g.spb - 1));
@@ -1647,37 +1655,48 @@ __global__ void __launch_bounds__(kThreads) k_mul(MulParams p) {
     const uint32_t sw = (cnt > 0 && w > 0) ? bswap32(S[seg]) : 0u;
     __syncthreads();
 
-    // inverse BF + inverse LZ: bins of the segment
-    int64_t e_of[32];
+    // inverse BF + inverse LZ: in-segment prefixes of the bins
+    const uint32_t* sp = &s_pay[1 + off];
+    int32_t r[32];
     int64_t D = 0;
-    {
+    if (cnt == 32 && w <= 20) {
+      if (w == 0) {
+#pragma unroll
+        for (int j = 0; j < 32; ++j) r[j] = 0;
+      } else {
+        D = prefix_fast(sp, w, sw, sub == 0, r);
+      }
+    } else if (cnt > 0) {
       int64_t E = 0;
       unsigned __int128 E2w = 0;
-      if (cnt > 0) {
-        D = decode_generic<true>(&s_pay[1 + off], sw, w, sub, cnt, E, E2w, e_of);
-      } else {
+      D = decode_generic<true, int32_t>(sp, sw, w, sub, cnt, E, E2w, r);
+    } else {
 #pragma unroll
-        for (int j = 0; j < 32; ++j) e_of[j] = 0;
-      }
+      for (int j = 0; j < 32; ++j) r[j] = 0;
     }
     const int64_t carry = int64_t(outlier) + block_excl(D, g.spb);
-    const bool check = cnt > 0 && !bins_surely_in_range(outlier, blen, w);
-    // scaled bins, then Lorenzo deltas of the result
-    int32_t r[32];
-#pragma unroll
-    for (int j = 0; j < 32; ++j) {
-      const int64_t bin = carry + e_of[j];
-      if (check && uint32_t(j) < cnt && (bin < -kBinMax || bin > kBinMax)) bad |= ST_FORMAT;
-      r[j] = uint32_t(j) < cnt ? scaled_bin(bin, p.k, bad) : 0;
+    // every input bin must be a valid int32 bin (slot 0 is the outlier itself)
+    if (cnt > 0 && !bins_surely_in_range(outlier, blen, w)) {
+      int64_t e = 0;
+      for (int j = 0; j < int(cnt); ++j) {
+        if (w && !(j == 0 && sub == 0)) e += seg_delta(sp, sw, w, j);
+        const int64_t bin = carry + e;
+        if (bin < -kBinMax || bin > kBinMax) bad |= ST_FORMAT;
+      }
     }
+    // scaled bins, in place
+    const uint32_t c32 = uint32_t(carry);
+#pragma unroll
+    for (int j = 0; j < 32; ++j)
+      r[j] = uint32_t(j) < cnt ? scaled_bin(int32_t(c32 + uint32_t(r[j])), p.k, bad) : 0;
     // last scaled bin of the previous segment of the same block (a segment
     // with valid slots after the first always follows a full segment)
     const int32_t prev = __shfl_up(r[31], 1, 64);
-    uint32_t mag[32];
     uint32_t sgn = 0, mx = 0;
     int32_t outlier_z = 0;
+    uint32_t mag[32];  // computed back to front, so each bin dies as its magnitude is made
 #pragma unroll
-    for (int j = 0; j < 32; ++j) {
+    for (int j = 31; j >= 0; --j) {
       bool neg = false;
       uint32_t m = 0;
       if (uint32_t(j) < cnt) {
@@ -1696,7 +1715,7 @@ __global__ void __launch_bounds__(kThreads) k_mul(MulParams p) {
     mx = block_max(mx, g.spb);
     const uint32_t wz = bitlen32(mx);
     uint32_t tw_z;
-    const uint32_t off_z = wg_scan(wz, tw_z, s_tmp);
+    const uint32_t off_z = wg_scan<NT>(wz, tw_z, s_tmp);
     // publish the output tile's size, then pack and store what needs no offset
     lb_publish(p.s.st_out, tile, tw_z, p.epoch);
     if (wz > 0) pack32(&s_pay[off_z], mag, wz);
@@ -1707,12 +1726,12 @@ __global__ void __launch_bounds__(kThreads) k_mul(MulParams p) {
       }
       reinterpret_cast<uint32_t*>(p.out + g.off_s)[seg] = bswap32(sgn);
     }
-    const uint64_t base_z = lb_wait(p.s.st_out, tile, tw_z, p.epoch, s_lb);
+    const uint64_t base_z = lb_wait<NT>(p.s.st_out, tile, tw_z, p.epoch, s_lb);
     if (tid == 0) next = atomicAdd(&p.s.ctrl[C_TICKET], 1u);
     __syncthreads();
     uint32_t* Pz = reinterpret_cast<uint32_t*>(p.out + g.off_p) + base_z;
-    for (uint32_t k = tid; k < tw_z; k += kThreads) Pz[k] = bswap32(s_pay[k]);
-    if (tid == 0 && tile == g.ntiles - 1) {
+    for (uint32_t k = tid; k < tw_z; k += NT) Pz[k] = bswap32(s_pay[k]);
+    if (tid == 0 && tile == ntiles - 1) {
       const uint64_t payload = 4 * (base_z + tw_z);
       write_header(p.out, g, payload);
       st_dev(&p.s.acc[A_OUT], g.off_p + payload);
@@ -1882,7 +1901,7 @@ hipError_t launch_mul(const Scratch& s, const Grids& gr, const uint8_t* c, uint6
   hipError_t e = launch_widths(s, gr, 0, c, c_bytes, st);
   if (e != hipSuccess) return e;
   MulParams p{c, c_bytes, out, out_cap, k, s, epoch, res};
-  hipLaunchKernelGGL(k_mul, dim3(gr.mul), dim3(kThreads), 0, st, p);
+  hipLaunchKernelGGL(k_mul<kMulThreads>, dim3(gr.mul), dim3(kMulThreads), 0, st, p);
   return hipGetLastError();
 }
 
@@ -1925,7 +1944,7 @@ hipError_t query_grids(Grids& gr, int num_cus) {
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&c, k_compress<1, kCompressThreads>, kCompressThreads, 0);
   if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&d, k_decode<kVariance>, kThreads, 0);
   if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_add, kThreads, 0);
-  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&m, k_mul, kThreads, 0);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&m, k_mul<kMulThreads>, kMulThreads, 0);
   if (e != hipSuccess) return e;
   auto clampg = [&](int occ) { return num_cus * (occ < 1 ? 1 : occ); };
   gr.compress = clampg(c);
