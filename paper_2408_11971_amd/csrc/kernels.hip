@@ -32,6 +32,7 @@ constexpr uint32_t kEpochLimit = 1u << 28;
 // larger tiles halve the serial look-back steps.
 constexpr int kCompressThreads = 1024;
 constexpr int kMulThreads = 1024;
+constexpr int kAddThreads = 1024;
   // look-back epochs are 28-bit, never 0
 
 enum { kMean = 0, kVariance = 1, kDecompress = 2 };
@@ -1436,13 +1437,17 @@ struct AddParams {
   hoszp_result* res;
 };
 
-__global__ void __launch_bounds__(kThreads) k_add(AddParams p) {
-  __shared__ uint32_t s_a[kTileWords + 2];
-  __shared__ uint32_t s_b[kTileWords + 2];
-  __shared__ uint32_t s_tmp[kThreads / 64];
+// Element-wise addition, one tile of NT segments per workgroup.  The two
+// operands' payloads are staged one after the other in the same LDS buffer:
+// A's magnitudes are held in registers while B's payload replaces A's, so the
+// workgroup needs one tile of LDS, not two.
+template <int NT>
+__global__ void __launch_bounds__(NT) k_add(AddParams p) {
+  __shared__ uint32_t s_pay[NT * 32 + 2];
+  __shared__ uint32_t s_tmp[NT / 64];
   __shared__ uint64_t s_ticket, s_base_a, s_base_b;
   __shared__ uint32_t s_flag;
-  __shared__ LbShared<> s_lb;
+  __shared__ LbShared<NT> s_lb;
   const int tid = threadIdx.x;
   Layout g, gb;
   uint32_t err = read_header(p.a, p.a_bytes, g);
@@ -1452,7 +1457,7 @@ __global__ void __launch_bounds__(kThreads) k_add(AddParams p) {
     err = ST_MISMATCH;
   if (!err && p.out_cap < bound_bytes(g.n, g.L)) err = ST_CAPACITY;
   if (tid == 0 && blockIdx.x == 0) latch(p.s, err);
-  const uint64_t ntiles = err ? 0 : g.ntiles;
+  const uint64_t ntiles = err ? 0 : (g.nseg + NT - 1) / NT;
   const uint32_t* Sa = reinterpret_cast<const uint32_t*>(p.a + g.off_s);
   const uint32_t* Sb = reinterpret_cast<const uint32_t*>(p.b + gb.off_s);
   const int32_t* Oa = reinterpret_cast<const int32_t*>(p.a + g.off_o);
@@ -1465,24 +1470,35 @@ __global__ void __launch_bounds__(kThreads) k_add(AddParams p) {
     const uint64_t tile = uni64(s_ticket);
     if (tile >= ntiles) break;
     if (tid < 64) {
-      const uint64_t v = tile_offset(p.s.idx[0], kWavesPerTile * tile);
+      const uint64_t v = tile_offset(p.s.idx[0], (NT / kWaveSegs) * tile);
       if (tid == 0) s_base_a = v;
     } else if (tid < 128) {
-      const uint64_t v = tile_offset(p.s.idx[1], kWavesPerTile * tile);
+      const uint64_t v = tile_offset(p.s.idx[1], (NT / kWaveSegs) * tile);
       if (tid == 64) s_base_b = v;
     }
-    uint32_t bad = 0;
-    uint32_t wa, wb, tw_a, tw_b;
-    const uint32_t off_a = stage_tile(p.a, g, tile, s_a, s_tmp, &s_base_a, wa, tw_a, bad);
-    const uint32_t off_b = stage_tile(p.b, gb, tile, s_b, s_tmp, &s_base_b, wb, tw_b, bad);
-    const uint64_t seg = tile * kTileSegs + tid;
+    const uint64_t seg = tile * NT + tid;
     const bool active = seg < g.nseg;
     const uint64_t blk = (seg >> g.spb_log2);
     const uint32_t sub = uint32_t(seg & (g.spb - 1));
     uint64_t blen = 0;
     const uint32_t cnt = active ? seg_count(g, blk, sub, blen) : 0u;
     const int64_t oa = active ? Oa[blk] : 0, ob = active ? Ob[blk] : 0;
+    uint32_t bad = 0;
+    // operand A: stage, then keep its magnitudes in registers
+    uint32_t wa, tw_a;
+    const uint32_t off_a = stage_tile<NT>(p.a, g, tile, s_pay, s_tmp, &s_base_a, wa, tw_a, bad);
     const uint32_t swa = (cnt > 0 && wa) ? bswap32(Sa[seg]) : 0u;
+    __syncthreads();
+    uint32_t ma[32];
+    {
+      const uint32_t* sp = &s_pay[1 + off_a];
+      const uint32_t ww = wa ? wa : 1u;  // width 0: fields read, then dropped
+#pragma unroll
+      for (int j = 0; j < 32; ++j) ma[j] = wa ? field(sp, uint32_t(j), ww) : 0u;
+    }
+    // operand B replaces A in LDS (stage_tile's scan barriers order the reuse)
+    uint32_t wb, tw_b;
+    const uint32_t off_b = stage_tile<NT>(p.b, gb, tile, s_pay, s_tmp, &s_base_b, wb, tw_b, bad);
     const uint32_t swb = (cnt > 0 && wb) ? bswap32(Sb[seg]) : 0u;
     __syncthreads();
 
@@ -1491,27 +1507,21 @@ __global__ void __launch_bounds__(kThreads) k_add(AddParams p) {
     uint32_t mag[32];
     uint32_t sgn = 0, mx = 0;
     int64_t D = 0;
-    const uint32_t* spa = &s_a[1 + off_a];
-    const uint32_t* spb = &s_b[1 + off_b];
+    const uint32_t* spb = &s_pay[1 + off_b];
     if (cnt == 32 && wa <= 30 && wb <= 30) {
       // |d_A + d_B| < 2^31: 32-bit arithmetic
-      const uint32_t ra = 32u - wa, rb = 32u - wb;
-      uint32_t pa = 0, pb = 0;
+      const uint32_t rb = 32u - wb;
+      uint32_t pb = 0;
       int32_t dsum = 0;
 #pragma unroll
       for (int j = 0; j < 32; ++j) {
-        int32_t d = 0;
-        if (wa) {
-          const int32_t m = int32_t(field_at(spa, pa, ra));
-          const int32_t s = int32_t(swa << j) >> 31;
-          d = (m ^ s) - s;
-        }
+        const int32_t sa = int32_t(swa << j) >> 31;
+        int32_t d = (int32_t(ma[j]) ^ sa) - sa;
         if (wb) {
           const int32_t m = int32_t(field_at(spb, pb, rb));
           const int32_t s = int32_t(swb << j) >> 31;
           d += (m ^ s) - s;
         }
-        pa += wa;
         pb += wb;
         if (j == 0 && sub == 0) d = 0;
         const uint32_t neg = uint32_t(d) >> 31;
@@ -1525,8 +1535,7 @@ __global__ void __launch_bounds__(kThreads) k_add(AddParams p) {
     } else {
 #pragma unroll
       for (int j = 0; j < 32; ++j) {
-        int64_t d = 0;
-        if (wa) d += seg_delta(spa, swa, wa, j);
+        int64_t d = ((swa >> (31 - j)) & 1u) ? -int64_t(ma[j]) : int64_t(ma[j]);
         if (wb) d += seg_delta(spb, swb, wb, j);
         if ((j == 0 && sub == 0) || uint32_t(j) >= cnt) d = 0;
         const bool neg = d < 0;
@@ -1548,7 +1557,7 @@ __global__ void __launch_bounds__(kThreads) k_add(AddParams p) {
         int64_t e = 0;
         for (int j = 0; j < int(cnt); ++j) {
           if (j > 0 || sub > 0) {
-            if (wa) e += seg_delta(spa, swa, wa, j);
+            if (wa) e += ((swa >> (31 - j)) & 1u) ? -int64_t(ma[j]) : int64_t(ma[j]);
             if (wb) e += seg_delta(spb, swb, wb, j);
           }
           const int64_t bin = carry + e;
@@ -1560,10 +1569,10 @@ __global__ void __launch_bounds__(kThreads) k_add(AddParams p) {
     mx = block_max(mx, g.spb);
     const uint32_t w = bitlen32(mx);
     uint32_t tw_z;
-    const uint32_t off_z = wg_scan(w, tw_z, s_tmp);  // barriers: all threads done reading s_a
+    const uint32_t off_z = wg_scan<NT>(w, tw_z, s_tmp);  // barriers: all threads done reading B
     // publish the output tile's size, then pack and store what needs no offset
     lb_publish(p.s.st_out, tile, tw_z, p.epoch);
-    if (w > 0) pack32(&s_a[off_z], mag, w);
+    if (w > 0) pack32(&s_pay[off_z], mag, w);
     if (active) {
       if (sub == 0) {
         p.out[g.off_w + blk] = uint8_t(w);
@@ -1571,12 +1580,12 @@ __global__ void __launch_bounds__(kThreads) k_add(AddParams p) {
       }
       reinterpret_cast<uint32_t*>(p.out + g.off_s)[seg] = bswap32(sgn);
     }
-    const uint64_t base_z = lb_wait(p.s.st_out, tile, tw_z, p.epoch, s_lb);
+    const uint64_t base_z = lb_wait<NT>(p.s.st_out, tile, tw_z, p.epoch, s_lb);
     if (tid == 0) next = atomicAdd(&p.s.ctrl[C_TICKET], 1u);
     __syncthreads();
     uint32_t* Pz = reinterpret_cast<uint32_t*>(p.out + g.off_p) + base_z;
-    for (uint32_t k = tid; k < tw_z; k += kThreads) Pz[k] = bswap32(s_a[k]);
-    if (tid == 0 && tile == g.ntiles - 1) {
+    for (uint32_t k = tid; k < tw_z; k += NT) Pz[k] = bswap32(s_pay[k]);
+    if (tid == 0 && tile == ntiles - 1) {
       const uint64_t payload = 4 * (base_z + tw_z);
       write_header(p.out, g, payload);
       st_dev(&p.s.acc[A_OUT], g.off_p + payload);
@@ -1891,7 +1900,7 @@ hipError_t launch_add(const Scratch& s, const Grids& gr, const uint8_t* a, uint6
   if (e == hipSuccess) e = launch_widths(s, gr, 1, b, b_bytes, st);
   if (e != hipSuccess) return e;
   AddParams p{a, a_bytes, b, b_bytes, out, out_cap, s, epoch, res};
-  hipLaunchKernelGGL(k_add, dim3(gr.add), dim3(kThreads), 0, st, p);
+  hipLaunchKernelGGL(k_add<kAddThreads>, dim3(gr.add), dim3(kAddThreads), 0, st, p);
   return hipGetLastError();
 }
 
@@ -1943,7 +1952,7 @@ hipError_t query_grids(Grids& gr, int num_cus) {
   int c = 0, d = 0, a = 0, m = 0;
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&c, k_compress<1, kCompressThreads>, kCompressThreads, 0);
   if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&d, k_decode<kVariance>, kThreads, 0);
-  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_add, kThreads, 0);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_add<kAddThreads>, kAddThreads, 0);
   if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&m, k_mul<kMulThreads>, kMulThreads, 0);
   if (e != hipSuccess) return e;
   auto clampg = [&](int occ) { return num_cus * (occ < 1 ? 1 : occ); };
