@@ -103,7 +103,7 @@ typedef struct hoszp_info {
 typedef struct hoszp_ctx hoszp_ctx;
 
 /* Create a context on HIP device `device` (allocates its scratch, about
- * 13 MB of device memory plus one pinned host record).  Returns HOSZP_OK and
+ * 22 MB of device memory plus one pinned host record).  Returns HOSZP_OK and
  * sets *out, or HOSZP_ERR_DEVICE / HOSZP_ERR_NOMEM. */
 int hoszp_ctx_create(int device, hoszp_ctx** out);
 
@@ -247,7 +247,7 @@ typedef struct hoszp_field_result {
 
 typedef struct hoszp_batch_info {
   uint64_t fields;
-  uint64_t total_tiles; /* work-list length (tiles of 8192 slots) */
+  uint64_t total_tiles; /* work-list length (tiles of 32768 slots) */
   uint64_t raw_bytes;   /* sum of 4 n over the fields */
   uint64_t device_bytes;/* device memory the plan holds */
   uint32_t grid;        /* persistent workgroups per launch */
@@ -260,7 +260,7 @@ typedef struct hoszp_batch hoszp_batch;
 
 /* Plan a batch: check every field (ARG / CAPACITY, with *bad_field set to the
  * first offending index when bad_field is not NULL), run the autotuner on
- * `stream`, allocate the plan's device state (about 8 bytes per 8192 input
+ * `stream`, allocate the plan's device state (about 12 bytes per 32768 input
  * elements plus 192 bytes per field), and capture the launch.  The field
  * table is copied; the buffers it points to must stay valid while the plan
  * is used.  Synchronizes `stream`. */
