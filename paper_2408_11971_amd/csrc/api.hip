@@ -97,21 +97,16 @@ bool stream_args_ok(hoszp_ctx* ctx, const void* d_c, hoszp_result* d_res) {
   return ctx && d_c && d_res && aligned(d_c, 16) && aligned(d_res, 8);
 }
 
-// s = m 2^-sh with |m| < 2^53 (see hz::MulScalar).
+// Classify the scalar s = m 2^e (|m| < 2^53) as the exact definition does:
+// e >= 0 makes every non-zero bin overflow, e < -100 makes every result 0.
 hz::MulScalar mul_split(double s) {
-  hz::MulScalar k{0, 1, 0};
+  hz::MulScalar k{s, 0, 0};
   int e2 = 0;
   const double frac = frexp(s, &e2);
   const int64_t m = int64_t(ldexp(frac, 53));
   const int e = e2 - 53;
-  if (m == 0) return k;
-  if (e >= 0) {
-    k.big = 1;
-    return k;
-  }
-  if (-e > 100) return k;  // |s q| < 2^-16: every result rounds to 0
-  k.m = m;
-  k.sh = -e;
+  if (m == 0 || -e > 100) k.zero = 1;  // |s q| < 2^-16: every result rounds to 0
+  else if (e >= 0) k.big = 1;
   return k;
 }
 

@@ -103,11 +103,11 @@ struct Scratch {
   uint32_t max_part;    // capacity of `part`
 };
 
-// Scalar multiplier s = m * 2^-sh split on the host (see mul_split()).
+// Scalar multiplier, classified on the host (see mul_split()).
 struct MulScalar {
-  int64_t m;    // |m| < 2^53
-  int32_t sh;   // shift in [1, 100]
+  double s;     // the scalar
   int32_t big;  // 1 when |s| >= 2^52: any non-zero bin overflows
+  int32_t zero; // 1 when |s q| < 2^-16 for every int32 q: every result is 0
 };
 
 // One field of a batched compress, as the kernel sees it.

@@ -1606,19 +1606,36 @@ struct MulParams {
   hoszp_result* res;
 };
 
-// floor(s q + 1/2) exactly, with s = m 2^-sh.
-__device__ __forceinline__ int32_t scaled_bin(int64_t q, const MulScalar& k, uint32_t& bad) {
+// floor(s q + 1/2) exactly, in binary64: y = fl(s q) and err = fma(s, q, -y)
+// give s q = y + err exactly (the FMA two-product error-free transformation,
+// no underflow since |s| >= 2^-100 and q != 0); with |y| <= 2^31, z = y + 1/2
+// and g = z - floor(z) are exact, and err only moves the floor by one when
+// it crosses an integer, which the two exact comparisons detect.
+__device__ __forceinline__ int32_t scaled_bin(int32_t q, const MulScalar& k, uint32_t& bad) {
   if (k.big) {
     if (q != 0) bad |= ST_RANGE;
     return 0;
   }
-  const __int128 prod = __int128(k.m) * __int128(q);
-  const __int128 r = (prod + (__int128(1) << (k.sh - 1))) >> k.sh;
-  if (r < -__int128(kBinMax) || r > __int128(kBinMax)) {
+  if (k.zero) return 0;
+  const double qd = double(q);
+  const double y = k.s * qd;
+  if (!(fabs(y) <= 2147483648.0)) {  // beyond the bin range
     bad |= ST_RANGE;
     return 0;
   }
-  return int32_t(r);
+  const double err = fma(k.s, qd, -y);
+  const double z = y + 0.5;
+  double f = floor(z);
+  const double g = z - f;
+  if (err < -g)
+    f -= 1.0;
+  else if (err >= 1.0 - g)
+    f += 1.0;
+  if (f < -kBinMaxD || f > kBinMaxD) {
+    bad |= ST_RANGE;
+    return 0;
+  }
+  return int32_t(f);
 }
 
 // Scalar multiplication, one tile of NT segments per workgroup: decode the

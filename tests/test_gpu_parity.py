@@ -302,3 +302,27 @@ def test_async_chain_matches_sync(dev):
     zc = ref.add(xc, xc)
     assert a3["out_bytes"] == zc.size
     assert np.array_equal(host(z)[:zc.size], zc)
+
+
+@pytest.mark.parametrize("s", [0.5, 1.5, -2.5, 1.0 / 3.0, 0.1, 3 * 2.0**-20, 1e-5, 123.456,
+                               -0.7499999999999999, 2.0**51 * 1.5, 2.0**-101])
+def test_mul_rounding_ties(dev, s):
+    """Integer-valued fields at eb = 1/2 (bins equal the values): scalars that
+    put s q exactly on, or one ulp beside, half-integers must round like the
+    exact definition."""
+    print(f"case mul ties s={s}", flush=True)
+    rng = np.random.default_rng(17)
+    q = rng.integers(-200000, 200001, 40000)
+    q[::7] = rng.integers(-3, 4, q[::7].size)
+    x = q.astype(np.float32)
+    xc = ref.compress(x, 0.5, 32)
+    c = hz.compress(gpu(x, dev), 0.5, 32)
+    assert np.array_equal(host(c), xc)
+    try:
+        want = ref.mul(xc, s)
+    except ref.RefError as e:
+        with pytest.raises(hz.HoszpError) as g:
+            hz.mul(c, s)
+        assert g.value.code == e.code
+        return
+    assert np.array_equal(host(hz.mul(c, s)), want), f"mul by {s!r}"
