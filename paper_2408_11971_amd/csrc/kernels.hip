@@ -1533,35 +1533,37 @@ __global__ void __launch_bounds__(NT) k_add(AddParams p) {
       }
       D = dsum;
     } else {
+      bool wide = false;
 #pragma unroll
       for (int j = 0; j < 32; ++j) {
         int64_t d = ((swa >> (31 - j)) & 1u) ? -int64_t(ma[j]) : int64_t(ma[j]);
         if (wb) d += seg_delta(spb, swb, wb, j);
         if ((j == 0 && sub == 0) || uint32_t(j) >= cnt) d = 0;
         const bool neg = d < 0;
-        // |d| >= 2^32 only happens when some bin of the sum is out of range,
-        // which the check below reports; the truncated field stays memory-safe
-        const uint32_t m = uint32_t(neg ? -d : d);
+        const uint64_t a = uint64_t(neg ? -d : d);
+        // |d| >= 2^32 means some bin of the sum is out of range
+        wide |= (a >> 32) != 0;
+        const uint32_t m = uint32_t(a);
         mag[j] = m;
         sgn |= uint32_t(neg) << (31 - j);
         mx = max(mx, m);
         D += d;
       }
+      if (wide) bad |= ST_RANGE;
     }
-    // every bin of the sum must stay in range
+    // every bin of the sum must stay in range (checked from the sum's own
+    // deltas, so A's magnitudes need not outlive the loop above)
     const int64_t carry = oz + block_excl(D, g.spb);
     if (cnt > 0) {
       const uint64_t aa = uint64_t(oa < 0 ? -oa : oa), ab = uint64_t(ob < 0 ? -ob : ob);
       const uint64_t sa = (uint64_t(1) << wa) - 1, sb = (uint64_t(1) << wb) - 1;
       if (aa + ab + (blen - 1) * (sa + sb) > uint64_t(kBinMax)) {
         int64_t e = 0;
-        for (int j = 0; j < int(cnt); ++j) {
-          if (j > 0 || sub > 0) {
-            if (wa) e += ((swa >> (31 - j)) & 1u) ? -int64_t(ma[j]) : int64_t(ma[j]);
-            if (wb) e += seg_delta(spb, swb, wb, j);
-          }
+#pragma unroll
+        for (int j = 0; j < 32; ++j) {
+          e += ((sgn >> (31 - j)) & 1u) ? -int64_t(mag[j]) : int64_t(mag[j]);
           const int64_t bin = carry + e;
-          if (bin < -kBinMax || bin > kBinMax) bad |= ST_RANGE;
+          if (uint32_t(j) < cnt && (bin < -kBinMax || bin > kBinMax)) bad |= ST_RANGE;
         }
       }
     }
