@@ -38,7 +38,7 @@ struct hoszp_batch {
 namespace {
 
 constexpr uint32_t kEpochMask = (1u << 28) - 1;
-constexpr uint32_t kMaxTiles = uint32_t((hz::kMaxN + hz::kTileSegs * 32ull) / (hz::kTileSegs * 32ull) + 1);
+constexpr uint32_t kMaxTiles = uint32_t((hz::kMaxN + hz::kMinTileSegs * 32ull) / (hz::kMinTileSegs * 32ull) + 1);
 constexpr uint32_t kMaxPart = 4096;
 
 class DeviceScope {
@@ -183,7 +183,7 @@ int hoszp_ctx_create(int device, hoszp_ctx** out) {
     return HOSZP_ERR_DEVICE;
   }
   auto up = [](size_t b) { return (b + 255) / 256 * 256; };  // every array 256-byte aligned
-  const size_t max_wtiles = size_t(kMaxTiles) * hz::kWavesPerTile;
+  const size_t max_wtiles = size_t(kMaxTiles) * (hz::kMinTileSegs / hz::kWaveSegs);
   const size_t nchunk = max_wtiles / hz::kChunkTiles + 2;
   const size_t ctrl_b = 256, acc_b = 256, part_b = up(size_t(kMaxPart) * sizeof(double));
   const size_t st_b = up(size_t(kMaxTiles) * sizeof(uint64_t));

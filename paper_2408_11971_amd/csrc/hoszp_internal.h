@@ -19,21 +19,22 @@ constexpr uint64_t kMaxN = 4294967295ULL; // n < 2^32
 // A block of L slots is cut into L/32 "segments" of 32 slots.  Because every
 // block contributes L * width bits to the payload, segment s of a block owns
 // exactly `width` 32-bit words of it, starting on a word boundary, and sign
-// word s of the block.  Every kernel processes one segment per thread and a
-// tile of kTileSegs segments (8192 slots) per workgroup.
+// word s of the block.  Every kernel processes one segment per thread.
+// Encoders (compress, add, mul, batch) take tiles of as many segments as
+// their workgroup has threads; the other kernels use kThreads-thread
+// workgroups.
 constexpr int kThreads = 256;
-constexpr int kTileSegs = kThreads;
-constexpr int kTileWords = kTileSegs * 32;  // worst-case payload words of a tile
+// Smallest encoder tile: sizes the look-back status words (kMaxTiles).
+constexpr int kMinTileSegs = kThreads;
 
 // Decoders work per wave on "wave tiles" of kWaveSegs segments (2048 slots),
 // with no workgroup barrier between tiles.  The width pre-pass stores every
 // wave tile's payload word count and, for every chunk of kChunkTiles wave
 // tiles, the exclusive prefix; a wave tile's offset is its chunk's prefix
-// plus at most 63 counts (one wave-wide load).  A workgroup tile (kTileSegs
-// segments) of the encoders is kTileSegs / kWaveSegs consecutive wave tiles.
+// plus at most 63 counts (one wave-wide load).  An encoder tile of NT
+// segments is NT / kWaveSegs consecutive wave tiles.
 constexpr int kWaveSegs = 64;
 constexpr int kWaveWords = kWaveSegs * 32;  // worst-case payload words of a wave tile
-constexpr int kWavesPerTile = kTileSegs / kWaveSegs;
 constexpr int kChunkTiles = 64;
 
 // ---- status bits latched by the kernels (bit = 1 << code) -----------------
@@ -46,7 +47,7 @@ constexpr uint32_t ST_CAPACITY = 1u << HOSZP_ERR_CAPACITY;
 
 // Section placement of a stream with n elements in blocks of L.
 struct Layout {
-  uint64_t n, nb, nseg, ntiles, nwtiles;  // nwtiles: wave tiles
+  uint64_t n, nb, nseg, nwtiles;  // nwtiles: wave tiles
   uint32_t L, spb;  // block size, segments per block
   uint32_t spb_log2;
   double eb;
@@ -65,7 +66,6 @@ __host__ __device__ inline void place(Layout& g, uint64_t n, uint32_t L, double 
   g.eb = eb;
   g.nb = (n + L - 1) / L;
   g.nseg = g.nb * g.spb;
-  g.ntiles = (g.nseg + kTileSegs - 1) / kTileSegs;
   g.nwtiles = (g.nseg + kWaveSegs - 1) / kWaveSegs;
   g.off_w = kHeaderBytes;
   g.off_o = round16(g.off_w + g.nb);

@@ -1,15 +1,18 @@
 // kernels.hip -- gfx950 kernels of the HoSZp library (arXiv 2408.11971).
 //
 // Work decomposition (shared by every kernel): a block of L slots is split
-// into L/32 segments of 32 slots.  One thread owns one segment, a workgroup of
-// 256 threads owns a tile of 256 segments (8192 slots).  A segment of a block
-// of width w owns exactly w payload words (32 slots x w bits), so payload
-// offsets are prefix sums of per-segment widths:
-//   - decoders get them from a width pre-pass (k_widths) that reads only the
-//     width section and stores per-tile word counts and per-chunk prefixes;
-//   - encoders (compress, add, mul) produce them with a single-pass decoupled
-//     look-back over per-tile word counts, with tiles taken from an atomic
-//     ticket so a tile only waits on tiles owned by running workgroups.
+// into L/32 segments of 32 slots and one thread owns one segment.  A segment
+// of a block of width w owns exactly w payload words (32 slots x w bits), so
+// payload offsets are prefix sums of per-segment widths:
+//   - decoders (mean, variance, decompress) work per wave on tiles of 64
+//     segments and get offsets from a width pre-pass (k_widths) that reads
+//     only the width section and stores per-tile word counts and per-chunk
+//     prefixes;
+//   - encoders (compress, add, mul, batch) work per workgroup on tiles of
+//     NT segments (1024 threads) and produce offsets with a single-pass
+//     decoupled look-back over per-tile word counts, with tiles taken from an
+//     atomic ticket so a tile only waits on tiles owned by running
+//     workgroups.
 // Payload words are staged in LDS as big-endian values (one byte swap per
 // word), so a w-bit field at bit p of a segment is one funnel shift
 // (v_alignbit) of two neighbouring LDS words.
@@ -335,12 +338,6 @@ __device__ __forceinline__ uint64_t lb_wait(uint64_t* st, uint64_t tile, uint64_
   return excl;
 }
 
-template <int NT = kThreads>
-__device__ __forceinline__ uint64_t wg_lookback(uint64_t* st, uint64_t tile, uint64_t agg,
-                                                uint32_t epoch, LbShared<NT>& sh) {
-  lb_publish(st, tile, agg, epoch);
-  return lb_wait<NT>(st, tile, agg, epoch, sh);
-}
 
 // Payload word offset of wave tile `tile` of a stream from its width
 // pre-pass.  Run by one whole wave; every lane gets the result.
