@@ -1605,36 +1605,54 @@ struct MulParams {
   hoszp_result* res;
 };
 
-// floor(s q + 1/2) exactly, in binary64: y = fl(s q) and err = fma(s, q, -y)
-// give s q = y + err exactly (the FMA two-product error-free transformation,
-// no underflow since |s| >= 2^-100 and q != 0); with |y| <= 2^31, z = y + 1/2
-// and g = z - floor(z) are exact, and err only moves the floor by one when
-// it crosses an integer, which the two exact comparisons detect.
-__device__ __forceinline__ int32_t scaled_bin(int32_t q, const MulScalar& k, uint32_t& bad) {
-  if (k.big) {
-    if (q != 0) bad |= ST_RANGE;
-    return 0;
-  }
-  if (k.zero) return 0;
+// floor(s q + 1/2) exactly, in binary64, without branches: y = fl(s q) and
+// err = fma(s, q, -y) give s q = y + err exactly (the FMA two-product
+// error-free transformation; no underflow since s is 0 or |s| >= 2^-48 and
+// q != 0 or y = 0); while |y| <= 2^52, z = y + 1/2 and g = z - floor(z) are
+// exact, and err only moves the floor by one when it crosses an integer,
+// which the two exact comparisons detect.  Beyond that |floor(z)| is far
+// outside the bin range (infinite or NaN when s q overflows), and the one
+// range check flags it.
+__device__ __forceinline__ int32_t scaled_bin(int32_t q, double s, uint32_t& bad) {
   const double qd = double(q);
-  const double y = k.s * qd;
-  if (!(fabs(y) <= 2147483648.0)) {  // beyond the bin range
-    bad |= ST_RANGE;
-    return 0;
-  }
-  const double err = fma(k.s, qd, -y);
+  const double y = s * qd;
+  const double err = fma(s, qd, -y);
   const double z = y + 0.5;
   double f = floor(z);
   const double g = z - f;
-  if (err < -g)
-    f -= 1.0;
-  else if (err >= 1.0 - g)
-    f += 1.0;
-  if (f < -kBinMaxD || f > kBinMaxD) {
-    bad |= ST_RANGE;
-    return 0;
+  f += err < -g ? -1.0 : 0.0;
+  f += err >= 1.0 - g ? 1.0 : 0.0;
+  const bool ok = fabs(f) <= kBinMaxD;
+  bad |= ok ? 0u : uint32_t(ST_RANGE);
+  return ok ? int32_t(f) : 0;
+}
+
+// Scale a segment's bins front to back and turn each at once into its output
+// delta's magnitude and sign, so an input bin dies as its delta is made.
+// Slot 0's delta needs the previous segment's last scaled bin: its scaled bin
+// is returned in z0 and its magnitude left for the caller.  FULL: every lane
+// of the wave holds 32 valid slots, so no slot needs a bounds test.
+template <bool FULL>
+__device__ __forceinline__ void scale_deltas(const int32_t* r, uint32_t c32, uint32_t cnt, double s,
+                                             uint32_t* mag, uint32_t& sgn, uint32_t& mx,
+                                             int32_t& z0, int32_t& zl, uint32_t& bad) {
+  z0 = (FULL || cnt > 0) ? scaled_bin(int32_t(c32 + uint32_t(r[0])), s, bad) : 0;
+  int32_t zp = z0;
+  mag[0] = 0;
+#pragma unroll
+  for (int j = 1; j < 32; ++j) {
+    uint32_t m = 0;
+    bool neg = false;
+    if (FULL || uint32_t(j) < cnt) {
+      const int32_t z = scaled_bin(int32_t(c32 + uint32_t(r[j])), s, bad);
+      m = delta_mag(z, zp, neg);
+      zp = z;
+    }
+    mag[j] = m;
+    sgn |= uint32_t(neg) << (31 - j);
+    mx = max(mx, m);
   }
-  return int32_t(f);
+  zl = zp;
 }
 
 // Scalar multiplication, one tile of NT segments per workgroup: decode the
@@ -1709,32 +1727,29 @@ __global__ void __launch_bounds__(NT) k_mul(MulParams p) {
         if (bin < -kBinMax || bin > kBinMax) bad |= ST_FORMAT;
       }
     }
-    // scaled bins, in place
+    // scaled bins and the output deltas (a zero multiplier scales by exactly 0)
     const uint32_t c32 = uint32_t(carry);
-#pragma unroll
-    for (int j = 0; j < 32; ++j)
-      r[j] = uint32_t(j) < cnt ? scaled_bin(int32_t(c32 + uint32_t(r[j])), p.k, bad) : 0;
+    const double sc = p.k.zero ? 0.0 : p.k.s;
+    uint32_t sgn = 0, mx = 0;
+    uint32_t mag[32];
+    int32_t z0, zp;
+    if (__all(cnt == 32))
+      scale_deltas<true>(r, c32, cnt, sc, mag, sgn, mx, z0, zp, bad);
+    else
+      scale_deltas<false>(r, c32, cnt, sc, mag, sgn, mx, z0, zp, bad);
     // last scaled bin of the previous segment of the same block (a segment
     // with valid slots after the first always follows a full segment)
-    const int32_t prev = __shfl_up(r[31], 1, 64);
-    uint32_t sgn = 0, mx = 0;
+    const int32_t prev = __shfl_up(zp, 1, 64);
     int32_t outlier_z = 0;
-    uint32_t mag[32];  // computed back to front, so each bin dies as its magnitude is made
-#pragma unroll
-    for (int j = 31; j >= 0; --j) {
-      bool neg = false;
-      uint32_t m = 0;
-      if (uint32_t(j) < cnt) {
-        if (j == 0) {
-          if (sub == 0) outlier_z = r[0];
-          else m = delta_mag(r[0], prev, neg);
-        } else {
-          m = delta_mag(r[j], r[j - 1], neg);
-        }
+    if (cnt > 0) {
+      if (sub == 0) {
+        outlier_z = z0;
+      } else {
+        bool neg = false;
+        mag[0] = delta_mag(z0, prev, neg);
+        sgn |= uint32_t(neg) << 31;
+        mx = max(mx, mag[0]);
       }
-      mag[j] = m;
-      sgn |= uint32_t(neg) << (31 - j);
-      mx = max(mx, m);
     }
     latch(p.s, bad);
     mx = block_max(mx, g.spb);
