@@ -401,19 +401,52 @@ __device__ __forceinline__ bool bins_surely_in_range(int64_t outlier, uint64_t b
   return a + (blen - 1) * step <= uint64_t(kBinMax);
 }
 
+// Stage na words from a, then nb words from b, into LDS as big-endian-decoded
+// values: a's at sp[1..na], b's at sp[na + 2..na + nb + 1], each range with a
+// zero guard word on both sides.  Every thread issues kStageUnroll loads before
+// it waits on any, so one memory round trip moves kStageUnroll * NT words.
+// (Only the words [0, na) of a and [0, nb) of b are read.)  COUNTED: skip, by
+// workgroup-uniform branches, the loads a round needs for no thread (fewer
+// loads for narrow tiles; which variant a kernel uses is a measured choice,
+// as the branches change its register allocation).
+constexpr int kStageUnroll = 16;
+template <int NT = kThreads, bool COUNTED = true>
+__device__ __forceinline__ void stage_words(uint32_t* sp, const uint32_t* a, uint32_t na,
+                                            const uint32_t* b, uint32_t nb) {
+  const uint32_t total = na + nb;
+  // word k (k < total) is (k < na ? a : bk)[k]
+  const uint32_t* bk = nb ? b - na : a;
+  for (uint32_t k0 = threadIdx.x; k0 < total; k0 += kStageUnroll * NT) {
+    uint32_t v[kStageUnroll];
+    // loads this round needs at most (workgroup-uniform); past the end a
+    // thread reloads the last word, so the loads carry no lane condition
+    const uint32_t nu = (total - (k0 - threadIdx.x) + NT - 1) / NT;
+#pragma unroll
+    for (int u = 0; u < kStageUnroll; ++u) {
+      const uint32_t k = min(k0 + uint32_t(u) * NT, total - 1);
+      if (!COUNTED || uint32_t(u) < nu) v[u] = (k < na ? a : bk)[k];
+    }
+#pragma unroll
+    for (int u = 0; u < kStageUnroll; ++u) {
+      const uint32_t k = k0 + uint32_t(u) * NT;
+      if (k < total) sp[1 + k + (k >= na ? 1u : 0u)] = bswap32(v[u]);
+    }
+  }
+  if (threadIdx.x == 0) {
+    sp[0] = 0;
+    sp[1 + na] = 0;
+    if (nb) sp[2 + total] = 0;
+  }
+}
+
 // Stage payload words [base, base + words) of a stream into LDS (sp[1..]) with
 // a zero guard word on each side.  Returns false when the range leaves the
 // payload section (nothing is read then).
 template <int NT = kThreads>
 __device__ __forceinline__ bool stage_payload(uint32_t* sp, const uint32_t* P, uint64_t base, uint32_t words,
-                              uint64_t payload_words) {
+                                              uint64_t payload_words) {
   const bool fits = base + words <= payload_words;
-  if (fits)
-    for (uint32_t k = threadIdx.x; k < words; k += NT) sp[1 + k] = bswap32(P[base + k]);
-  if (threadIdx.x == 0) {
-    sp[0] = 0;
-    sp[1 + words] = 0;
-  }
+  stage_words<NT>(sp, P + base, fits ? words : 0u, nullptr, 0u);
   return fits;
 }
 
@@ -1481,11 +1514,37 @@ __global__ void __launch_bounds__(NT) k_add(AddParams p) {
     const uint32_t cnt = active ? seg_count(g, blk, sub, blen) : 0u;
     const int64_t oa = active ? Oa[blk] : 0, ob = active ? Ob[blk] : 0;
     uint32_t bad = 0;
-    // operand A: stage, then keep its magnitudes in registers
-    uint32_t wa, tw_a;
-    const uint32_t off_a = stage_tile<NT>(p.a, g, tile, s_pay, s_tmp, &s_base_a, wa, tw_a, bad);
+    // widths of both operands, scanned together in the 16-bit halves of one
+    // word (a tile holds at most 32 NT payload words per operand)
+    static_assert(NT * 32 < 65536, "tile word counts must fit 16 bits");
+    uint32_t wa = active ? p.a[g.off_w + blk] : 0u, wb = active ? p.b[gb.off_w + blk] : 0u;
+    if (wa > 32 || wb > 32) {
+      bad |= ST_FORMAT;
+      wa = wa > 32 ? 0u : wa;
+      wb = wb > 32 ? 0u : wb;
+    }
+    uint32_t tw2;
+    const uint32_t off2 = wg_scan<NT>(wa | (wb << 16), tw2, s_tmp);  // its barriers publish the bases
+    const uint32_t off_a = off2 & 0xffffu, off_b = off2 >> 16;
+    const uint32_t tw_a = tw2 & 0xffffu, tw_b = tw2 >> 16;
+    const uint32_t* Pa = reinterpret_cast<const uint32_t*>(p.a + g.off_p);
+    const uint32_t* Pb = reinterpret_cast<const uint32_t*>(p.b + gb.off_p);
+    // both payloads in LDS at once when they fit (B right after A's guard
+    // word), so their loads are in flight together; else B replaces A later
+    const bool both = tw_a + tw_b + 1 <= uint32_t(NT * 32);
+    const uint64_t base_a = uni64(s_base_a), base_b = uni64(s_base_b);
+    const bool fits_a = base_a + tw_a <= g.payload_bytes / 4;
+    const bool fits_b = base_b + tw_b <= gb.payload_bytes / 4;
+    if (!fits_a || !fits_b) bad |= ST_FORMAT;  // then nothing is read
+    if (both)
+      stage_words<NT, false>(s_pay, Pa + base_a, fits_a && fits_b ? tw_a : 0u, Pb + base_b,
+                      fits_a && fits_b ? tw_b : 0u);
+    else
+      stage_words<NT, false>(s_pay, Pa + base_a, fits_a ? tw_a : 0u, nullptr, 0u);
     const uint32_t swa = (cnt > 0 && wa) ? bswap32(Sa[seg]) : 0u;
+    const uint32_t swb = (cnt > 0 && wb) ? bswap32(Sb[seg]) : 0u;
     __syncthreads();
+    // operand A's magnitudes are kept in registers
     uint32_t ma[32];
     {
       const uint32_t* sp = &s_pay[1 + off_a];
@@ -1493,18 +1552,19 @@ __global__ void __launch_bounds__(NT) k_add(AddParams p) {
 #pragma unroll
       for (int j = 0; j < 32; ++j) ma[j] = wa ? field(sp, uint32_t(j), ww) : 0u;
     }
-    // operand B replaces A in LDS (stage_tile's scan barriers order the reuse)
-    uint32_t wb, tw_b;
-    const uint32_t off_b = stage_tile<NT>(p.b, gb, tile, s_pay, s_tmp, &s_base_b, wb, tw_b, bad);
-    const uint32_t swb = (cnt > 0 && wb) ? bswap32(Sb[seg]) : 0u;
-    __syncthreads();
+    const uint32_t* spb = &s_pay[tw_a + 2 + off_b];
+    if (!both) {
+      __syncthreads();  // every lane is done reading A
+      stage_words<NT, false>(s_pay, Pb + base_b, fits_b ? tw_b : 0u, nullptr, 0u);
+      __syncthreads();
+      spb = &s_pay[1 + off_b];
+    }
 
     // O_{A+B} = O_A + O_B, P_{A+B} = P_A + P_B (signed), then re-encode
     const int64_t oz = oa + ob;
     uint32_t mag[32];
     uint32_t sgn = 0, mx = 0;
     int64_t D = 0;
-    const uint32_t* spb = &s_pay[1 + off_b];
     if (cnt == 32 && wa <= 30 && wb <= 30) {
       // |d_A + d_B| < 2^31: 32-bit arithmetic
       const uint32_t rb = 32u - wb;
