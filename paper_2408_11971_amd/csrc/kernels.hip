@@ -345,9 +345,11 @@ __device__ __forceinline__ uint64_t tile_offset(const TileIndex& ix, uint64_t ti
   const int lane = threadIdx.x & 63;
   const uint64_t chunk = tile / kChunkTiles;
   const uint32_t r = uint32_t(tile % kChunkTiles);
-  uint64_t v = uint32_t(lane) < r ? ix.tile_words[chunk * kChunkTiles + lane] : 0u;
-  v = wave_sum(v);
-  return ix.chunk_off[chunk] + v;
+  // both loads issued before either is waited on (lanes past r load the
+  // chunk's first word and drop it)
+  const uint32_t t = ix.tile_words[chunk * kChunkTiles + (uint32_t(lane) < r ? lane : 0)];
+  const uint64_t c = ix.chunk_off[chunk];
+  return c + wave_sum(uint32_t(lane) < r ? uint64_t(t) : 0u);
 }
 
 // ------------------------------------------------------ segment primitives
@@ -1093,27 +1095,6 @@ __device__ __forceinline__ int64_t decode_generic(const uint32_t* sp, uint32_t s
   return e;
 }
 
-// Load the widths of a tile, scan them, and stage its payload words in LDS.
-// *s_base holds the tile's payload word offset once the scan's barriers have
-// passed.  Returns the segment's word offset in the tile.
-template <int NT = kThreads>
-__device__ __forceinline__ uint32_t stage_tile(const uint8_t* c, const Layout& g, uint64_t tile,
-                                               uint32_t* s_pay, uint32_t* s_tmp,
-                                               const uint64_t* s_base, uint32_t& w,
-                                               uint32_t& tile_words, uint32_t& bad) {
-  const uint64_t seg = tile * NT + threadIdx.x;
-  w = seg < g.nseg ? c[g.off_w + (seg >> g.spb_log2)] : 0u;
-  if (w > 32) {
-    bad |= ST_FORMAT;
-    w = 0;
-  }
-  const uint32_t off = wg_scan<NT>(w, tile_words, s_tmp);  // its barriers publish *s_base
-  const uint64_t base = uni64(*s_base);
-  const uint32_t* P = reinterpret_cast<const uint32_t*>(c + g.off_p);
-  if (!stage_payload<NT>(s_pay, P, base, tile_words, g.payload_bytes / 4)) bad |= ST_FORMAT;
-  return off;
-}
-
 // Raw loads of a wave tile's metadata, issued two tiles ahead of use: the
 // lane's block width and outlier, and the tile's payload offset inputs (its
 // chunk's prefix and one per-tile word count per lane).
@@ -1512,12 +1493,18 @@ __global__ void __launch_bounds__(NT) k_add(AddParams p) {
     const uint32_t sub = uint32_t(seg & (g.spb - 1));
     uint64_t blen = 0;
     const uint32_t cnt = active ? seg_count(g, blk, sub, blen) : 0u;
-    const int64_t oa = active ? Oa[blk] : 0, ob = active ? Ob[blk] : 0;
+    // per-segment metadata: every lane loads (an inactive lane block 0's,
+    // then drops it), so the loads carry no condition and overlap
+    const uint64_t mblk = active ? blk : 0, mseg = active ? seg : 0;
+    const int32_t oa32 = Oa[mblk], ob32 = Ob[mblk];
+    const uint32_t wa8 = p.a[g.off_w + mblk], wb8 = p.b[gb.off_w + mblk];
+    const uint32_t swa8 = Sa[mseg], swb8 = Sb[mseg];
+    const int64_t oa = active ? oa32 : 0, ob = active ? ob32 : 0;
     uint32_t bad = 0;
     // widths of both operands, scanned together in the 16-bit halves of one
     // word (a tile holds at most 32 NT payload words per operand)
     static_assert(NT * 32 < 65536, "tile word counts must fit 16 bits");
-    uint32_t wa = active ? p.a[g.off_w + blk] : 0u, wb = active ? p.b[gb.off_w + blk] : 0u;
+    uint32_t wa = active ? wa8 : 0u, wb = active ? wb8 : 0u;
     if (wa > 32 || wb > 32) {
       bad |= ST_FORMAT;
       wa = wa > 32 ? 0u : wa;
@@ -1541,8 +1528,8 @@ __global__ void __launch_bounds__(NT) k_add(AddParams p) {
                       fits_a && fits_b ? tw_b : 0u);
     else
       stage_words<NT, false>(s_pay, Pa + base_a, fits_a ? tw_a : 0u, nullptr, 0u);
-    const uint32_t swa = (cnt > 0 && wa) ? bswap32(Sa[seg]) : 0u;
-    const uint32_t swb = (cnt > 0 && wb) ? bswap32(Sb[seg]) : 0u;
+    const uint32_t swa = (cnt > 0 && wa) ? bswap32(swa8) : 0u;
+    const uint32_t swb = (cnt > 0 && wb) ? bswap32(swb8) : 0u;
     __syncthreads();
     // operand A's magnitudes are kept in registers
     uint32_t ma[32];
@@ -1745,17 +1732,30 @@ __global__ void __launch_bounds__(NT) k_mul(MulParams p) {
       const uint64_t v = tile_offset(p.s.idx[0], (NT / kWaveSegs) * tile);
       if (tid == 0) s_base = v;
     }
-    uint32_t bad = 0;
-    uint32_t w, tile_words;
-    const uint32_t off = stage_tile<NT>(p.c, g, tile, s_pay, s_tmp, &s_base, w, tile_words, bad);
     const uint64_t seg = tile * NT + tid;
     const bool active = seg < g.nseg;
     const uint64_t blk = (seg >> g.spb_log2);
     const uint32_t sub = uint32_t(seg & (g.spb - 1));
+    // per-segment metadata: every lane loads (an inactive lane block 0's,
+    // then drops it), so the loads carry no condition and overlap
+    const uint64_t mblk = active ? blk : 0, mseg = active ? seg : 0;
+    const int32_t o32 = O[mblk];
+    const uint32_t w8 = p.c[g.off_w + mblk];
+    const uint32_t s32 = S[mseg];
+    uint32_t bad = 0;
+    uint32_t w = active ? w8 : 0u;
+    if (w > 32) {
+      bad |= ST_FORMAT;
+      w = 0;
+    }
+    uint32_t tile_words;
+    const uint32_t off = wg_scan<NT>(w, tile_words, s_tmp);  // its barriers publish s_base
+    const uint32_t* P = reinterpret_cast<const uint32_t*>(p.c + g.off_p);
+    if (!stage_payload<NT>(s_pay, P, uni64(s_base), tile_words, g.payload_bytes / 4)) bad |= ST_FORMAT;
     uint64_t blen = 0;
     const uint32_t cnt = active ? seg_count(g, blk, sub, blen) : 0u;
-    const int32_t outlier = active ? O[blk] : 0;
-    const uint32_t sw = (cnt > 0 && w > 0) ? bswap32(S[seg]) : 0u;
+    const int32_t outlier = active ? o32 : 0;
+    const uint32_t sw = (cnt > 0 && w > 0) ? bswap32(s32) : 0u;
     __syncthreads();
 
     // inverse BF + inverse LZ: in-segment prefixes of the bins
