@@ -73,20 +73,47 @@ __device__ __forceinline__ void st_dev32(uint32_t* p, uint32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ uint32_t wave_min(uint32_t v) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) v = min(v, uint32_t(__shfl_xor(v, d, 64)));
-  return v;
+// Wave reductions (call with every lane of the wave active; the result is
+// wave-uniform).  Butterfly steps inside each 32-lane half use ds_swizzle's
+// bit-mask mode (lane i reads lane i ^ M), whose pattern is an immediate, so
+// no lane-index registers stay live; the two halves join through readlane.
+template <int M>
+__device__ __forceinline__ uint32_t swz_xor(uint32_t v) {
+  return uint32_t(__builtin_amdgcn_ds_swizzle(int(v), 0x1f | (M << 10)));
 }
-__device__ __forceinline__ uint64_t wave_sum(uint64_t v) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-  return v;
+__device__ __forceinline__ uint32_t lane_of(uint32_t v, int lane) {
+  return uint32_t(__builtin_amdgcn_readlane(int(v), lane));
+}
+__device__ __forceinline__ uint32_t wave_min(uint32_t v) {
+  v = min(v, swz_xor<1>(v));
+  v = min(v, swz_xor<2>(v));
+  v = min(v, swz_xor<4>(v));
+  v = min(v, swz_xor<8>(v));
+  v = min(v, swz_xor<16>(v));
+  return min(lane_of(v, 0), lane_of(v, 32));
 }
 __device__ __forceinline__ uint32_t wave_sum32(uint32_t v) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-  return v;
+  v += swz_xor<1>(v);
+  v += swz_xor<2>(v);
+  v += swz_xor<4>(v);
+  v += swz_xor<8>(v);
+  v += swz_xor<16>(v);
+  return lane_of(v, 0) + lane_of(v, 32);
+}
+template <int M>
+__device__ __forceinline__ uint64_t swz_add64(uint64_t v) {
+  const uint64_t o = (uint64_t(swz_xor<M>(uint32_t(v >> 32))) << 32) | swz_xor<M>(uint32_t(v));
+  return v + o;
+}
+__device__ __forceinline__ uint64_t wave_sum(uint64_t v) {
+  v = swz_add64<1>(v);
+  v = swz_add64<2>(v);
+  v = swz_add64<4>(v);
+  v = swz_add64<8>(v);
+  v = swz_add64<16>(v);
+  const uint64_t a = (uint64_t(lane_of(uint32_t(v >> 32), 0)) << 32) | lane_of(uint32_t(v), 0);
+  const uint64_t b = (uint64_t(lane_of(uint32_t(v >> 32), 32)) << 32) | lane_of(uint32_t(v), 32);
+  return a + b;
 }
 
 // Count this workgroup as finished on `counter`.  True (uniform) in the last
