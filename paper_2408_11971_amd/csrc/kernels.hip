@@ -116,6 +116,31 @@ __device__ __forceinline__ uint64_t wave_sum(uint64_t v) {
   return a + b;
 }
 
+// Inclusive scan over the wave (every lane active) with DPP row shifts
+// inside each row of 16 lanes, then the row broadcasts of lane 15 and lane
+// 31 across rows; a lane adds a moved value only where its source lane lies
+// before it.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_mov(uint32_t v) {
+  return uint32_t(__builtin_amdgcn_mov_dpp(int(v), CTRL, 0xf, 0xf, false));
+}
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+  const uint32_t lane = threadIdx.x & 63, rl = lane & 15;
+  uint32_t t = dpp_mov<0x111>(x);  // row_shr:1
+  x += rl >= 1 ? t : 0u;
+  t = dpp_mov<0x112>(x);  // row_shr:2
+  x += rl >= 2 ? t : 0u;
+  t = dpp_mov<0x114>(x);  // row_shr:4
+  x += rl >= 4 ? t : 0u;
+  t = dpp_mov<0x118>(x);  // row_shr:8
+  x += rl >= 8 ? t : 0u;
+  t = dpp_mov<0x142>(x);  // row_bcast:15
+  x += (lane & 31) >= 16 ? t : 0u;
+  t = dpp_mov<0x143>(x);  // row_bcast:31
+  x += lane >= 32 ? t : 0u;
+  return x;
+}
+
 // Count this workgroup as finished on `counter`.  True (uniform) in the last
 // workgroup to finish.  Everything a last workgroup reads from the others
 // travels through device-scope atomics (performed at the device coherence
@@ -202,12 +227,7 @@ __device__ __forceinline__ void write_header(uint8_t* out, const Layout& g, uint
 template <int NT = kThreads>
 __device__ __forceinline__ uint32_t wg_scan(uint32_t v, uint32_t& total, uint32_t* tmp) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  uint32_t x = v;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const uint32_t y = __shfl_up(x, d, 64);
-    if (lane >= d) x += y;
-  }
+  const uint32_t x = wave_incl_scan(v);
   if (lane == 63) tmp[wave] = x;
   __syncthreads();
   uint32_t before = 0, all = 0;
@@ -1171,15 +1191,10 @@ __device__ __forceinline__ void meta_b(const Layout& g, const uint32_t* S, const
   const uint32_t sub = uint32_t(seg & (g.spb - 1));
   uint64_t blen = 0;
   const uint32_t cnt = (wt < nwt && seg < g.nseg) ? seg_count(g, blk, sub, blen) : 0u;
-  uint32_t x = w;  // inclusive scan of the widths over the wave
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const uint32_t y = __shfl_up(x, d, 64);
-    if (lane >= d) x += y;
-  }
+  const uint32_t x = wave_incl_scan(w);  // inclusive scan of the widths over the wave
   m.w = w;
   m.off = x - w;
-  m.words = uni32(__shfl(x, 63, 64));
+  m.words = lane_of(x, 63);
   m.outlier = a.outlier;
   m.base = a.chunk_off + wave_sum(uint64_t(a.tw));
   m.sw = (cnt > 0 && w > 0) ? S[seg] : 0u;
