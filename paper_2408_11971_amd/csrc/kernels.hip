@@ -412,9 +412,12 @@ __device__ __forceinline__ uint32_t seg_count(const Layout& g, uint64_t blk, uin
 
 // w-bit field starting at bit p of a segment whose words start at sp (sp[-1]
 // and the word after the segment must be readable LDS words); rshift = 32 - w.
+__device__ __forceinline__ uint32_t window_at(const uint32_t* sp, uint32_t p) {
+  const uint32_t i = (p + 31u) >> 5;  // the 32 bits from bit p on (MSB first)
+  return __builtin_amdgcn_alignbit(sp[int(i) - 1], sp[i], 0u - p);
+}
 __device__ __forceinline__ uint32_t field_at(const uint32_t* sp, uint32_t p, uint32_t rshift) {
-  const uint32_t i = (p + 31u) >> 5;
-  return __builtin_amdgcn_alignbit(sp[int(i) - 1], sp[i], 0u - p) >> rshift;
+  return window_at(sp, p) >> rshift;
 }
 
 __device__ __forceinline__ uint32_t field(const uint32_t* sp, uint32_t j, uint32_t w) {
@@ -1042,20 +1045,26 @@ __device__ __forceinline__ uint32_t weighted_popcount(uint32_t v) {
 // The same pass also yields D = the delta total (sum_i x_i + popcount(signs),
 // slot 0 of a block excluded).  sum_i (32 - i) x_i is accumulated as the sum
 // of the running prefixes of x, one dependent add each, so no field value
-// outlives its own step.
+// outlives its own step.  PAIR (width <= 16): one 32-bit window holds two
+// whole fields, so one LDS read and funnel shift serve both.
+template <bool PAIR>
 __device__ __forceinline__ int32_t mean_fast(const uint32_t* sp, uint32_t w, uint32_t signs,
                                              bool first_seg, int32_t& D) {
   const uint32_t rs = 32u - w;
   int32_t run = 0, acc = 0;
   uint32_t pbit = 0;
-#pragma unroll
-  for (int j = 0; j < 32; ++j) {
-    const int32_t m = int32_t(field_at(sp, pbit, rs));
-    pbit += w;
+  auto step = [&](int32_t m, int j) {
     int32_t x = m ^ (int32_t(signs << j) >> 31);
     if (j == 0 && first_seg) x = 0;
     run += x;
     acc += run;
+  };
+#pragma unroll
+  for (int j = 0; j < 32; j += PAIR ? 2 : 1) {
+    const uint32_t win = window_at(sp, pbit);
+    pbit += PAIR ? 2 * w : w;
+    step(int32_t(win >> rs), j);
+    if (PAIR) step(int32_t((win << w) >> rs), j + 1);
   }
   D = run + int32_t(__popc(signs));
   return acc + int32_t(weighted_popcount(signs));
@@ -1063,22 +1072,27 @@ __device__ __forceinline__ int32_t mean_fast(const uint32_t* sp, uint32_t w, uin
 
 // Fast path of a full segment (width 1..20) for the variance: E = sum e_j
 // (int32), E2 = sum e_j^2 (int64), D = delta total.
+template <bool PAIR>
 __device__ __forceinline__ void var_fast(const uint32_t* sp, uint32_t w, uint32_t sw,
                                          bool first_seg, int32_t& E, int64_t& E2, int32_t& D) {
   const uint32_t rs = 32u - w;
   int32_t e = 0, s1 = 0;
   int64_t s2 = 0;
   uint32_t pbit = 0;
-#pragma unroll
-  for (int j = 0; j < 32; ++j) {
-    const int32_t m = int32_t(field_at(sp, pbit, rs));
-    pbit += w;
+  auto step = [&](int32_t m, int j) {
     const int32_t neg = int32_t(sw << j) >> 31;
     int32_t d = (m ^ neg) - neg;
     if (j == 0 && first_seg) d = 0;
     e += d;
     s1 += e;
     s2 += int64_t(e) * e;
+  };
+#pragma unroll
+  for (int j = 0; j < 32; j += PAIR ? 2 : 1) {
+    const uint32_t win = window_at(sp, pbit);
+    pbit += PAIR ? 2 * w : w;
+    step(int32_t(win >> rs), j);
+    if (PAIR) step(int32_t((win << w) >> rs), j + 1);
   }
   E = s1;
   E2 = s2;
@@ -1087,20 +1101,25 @@ __device__ __forceinline__ void var_fast(const uint32_t* sp, uint32_t w, uint32_
 
 // Fast path of a full segment (width 1..20) for decompression: the in-segment
 // prefixes (modulo 2^32; the bins they lead to are int32).
+template <bool PAIR>
 __device__ __forceinline__ int32_t prefix_fast(const uint32_t* sp, uint32_t w, uint32_t sw,
                                                bool first_seg, int32_t* e_out) {
   const uint32_t rs = 32u - w;
   int32_t e = 0;
   uint32_t pbit = 0;
-#pragma unroll
-  for (int j = 0; j < 32; ++j) {
-    const int32_t m = int32_t(field_at(sp, pbit, rs));
-    pbit += w;
+  auto step = [&](int32_t m, int j) {
     const int32_t neg = int32_t(sw << j) >> 31;
     int32_t d = (m ^ neg) - neg;
     if (j == 0 && first_seg) d = 0;
     e += d;
     e_out[j] = e;
+  };
+#pragma unroll
+  for (int j = 0; j < 32; j += PAIR ? 2 : 1) {
+    const uint32_t win = window_at(sp, pbit);
+    pbit += PAIR ? 2 * w : w;
+    step(int32_t(win >> rs), j);
+    if (PAIR) step(int32_t((win << w) >> rs), j + 1);
   }
   return e;
 }
@@ -1215,7 +1234,8 @@ __device__ __forceinline__ void meta_b(const Layout& g, const uint32_t* S, const
 // offsets are loaded two tiles ahead, sign words and the first payload words
 // one tile ahead, so memory latency overlaps the current tile's arithmetic.
 template <int MODE>
-__global__ void __launch_bounds__(kThreads) k_decode(DecodeParams p) {
+__global__ void __launch_bounds__(kThreads)
+    __attribute__((amdgpu_waves_per_eu(MODE == kDecompress ? 1 : 4))) k_decode(DecodeParams p) {
   // per-wave payload staging, reused by decompression to transpose its output
   __shared__ __align__(16) uint32_t s_pay[kThreads / 64][kWaveWords + 4];
   __shared__ uint32_t s_flag;
@@ -1294,17 +1314,22 @@ __global__ void __launch_bounds__(kThreads) k_decode(DecodeParams p) {
       } else if (MODE == kMean) {
         const uint32_t signs = sub == 0 ? (sw & 0x7fffffffu) : sw;  // slot 0: the outlier
         int32_t d1;
-        E = mean_fast(sp, w, signs, sub == 0, d1);
+        E = w <= 16 ? mean_fast<true>(sp, w, signs, sub == 0, d1)
+                    : mean_fast<false>(sp, w, signs, sub == 0, d1);
         D = d1;
       } else if (MODE == kVariance) {
         int32_t e1, d1;
         int64_t e2;
-        var_fast(sp, w, sw, sub == 0, e1, e2, d1);
+        if (w <= 16)
+          var_fast<true>(sp, w, sw, sub == 0, e1, e2, d1);
+        else
+          var_fast<false>(sp, w, sw, sub == 0, e1, e2, d1);
         E = e1;
         E2 = uint64_t(e2);
         D = d1;
       } else {
-        D = prefix_fast(sp, w, sw, sub == 0, keep32);
+        D = w <= 16 ? prefix_fast<true>(sp, w, sw, sub == 0, keep32)
+                    : prefix_fast<false>(sp, w, sw, sub == 0, keep32);
       }
     } else if (cnt > 0) {
       D = decode_generic<MODE == kDecompress, int32_t>(sp, sw, w, sub, cnt, E, E2w, keep32);
@@ -1809,7 +1834,8 @@ __global__ void __launch_bounds__(NT) k_mul(MulParams p) {
 #pragma unroll
         for (int j = 0; j < 32; ++j) r[j] = 0;
       } else {
-        D = prefix_fast(sp, w, sw, sub == 0, r);
+        D = w <= 16 ? prefix_fast<true>(sp, w, sw, sub == 0, r)
+                    : prefix_fast<false>(sp, w, sw, sub == 0, r);
       }
     } else if (cnt > 0) {
       int64_t E = 0;
