@@ -1441,58 +1441,78 @@ __global__ void __launch_bounds__(kThreads) k_negate(NegateParams p) {
   uint32_t err = read_header(p.c, p.c_bytes, g);
   if (!err && p.out_cap < g.total_bytes) err = ST_CAPACITY;
   if (tid == 0 && blockIdx.x == 0) latch(p.s, err);
-  const uint64_t nchunk = err ? 0 : (g.total_bytes + 15) / 16;  // total is a multiple of 4
+  const uint64_t nfull = err ? 0 : g.total_bytes / 16;  // whole 16-byte chunks
   const uint64_t stride = uint64_t(gridDim.x) * kThreads;
   uint64_t wsum = 0;
   uint32_t bad = 0;
   const uint4* src = reinterpret_cast<const uint4*>(p.c);
   uint4* dst = reinterpret_cast<uint4*>(p.out);
+  const uint32_t* W32 = reinterpret_cast<const uint32_t*>(p.c + g.off_w);  // 16-byte aligned
   const uint64_t w_end = g.off_w + g.nb, o_end = g.off_o + 4 * g.nb, s_end = g.off_s + 4 * g.nseg;
-  for (uint64_t k = uint64_t(blockIdx.x) * kThreads + tid; k < nchunk; k += stride) {
-    const uint64_t o = 16 * k;
-    if (o + 16 > g.total_bytes) {  // last partial chunk: payload words only
-      for (uint64_t b = o; b < g.total_bytes; b += 4)
-        *reinterpret_cast<uint32_t*>(p.out + b) = *reinterpret_cast<const uint32_t*>(p.c + b);
-      continue;
+  // Each thread moves kNegUnroll chunks per round, all loaded before any is
+  // written (no lane condition on the loads: past the end a thread reloads the
+  // last chunk and drops it), so the loads of a round are in flight together.
+  constexpr int kNegUnroll = 4;
+  for (uint64_t k0 = uint64_t(blockIdx.x) * kThreads + tid; k0 < nfull; k0 += kNegUnroll * stride) {
+    uint4 v[kNegUnroll];
+    uint32_t wq[kNegUnroll];  // sign chunks: the aligned width word holding their blocks
+#pragma unroll
+    for (int u = 0; u < kNegUnroll; ++u) {
+      const uint64_t k = min(k0 + uint64_t(u) * stride, nfull - 1);
+      v[u] = src[k];
+      const uint64_t o = 16 * k;
+      // a sign chunk's four segments are consecutive and start at a multiple
+      // of 4, so their blocks lie in one aligned 4-byte word of the widths
+      const uint64_t sg = (o >= g.off_s && o < s_end) ? (o - g.off_s) / 4 : 0;
+      wq[u] = W32[(sg >> g.spb_log2) >> 2];
     }
-    uint4 v = src[k];
-    uint32_t wd[4] = {v.x, v.y, v.z, v.w};
-    if (o >= g.off_p || o + 16 <= g.off_w) {
-      // header or payload: copy
-    } else if (o < g.off_o) {  // widths (and the padding after them)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const uint64_t b0 = o + 4 * q;
-        uint32_t x = wd[q];
-        if (b0 >= w_end) continue;
-        if (b0 + 4 > w_end) x &= 0xffffffffu >> (8 * (b0 + 4 - w_end));
-        if ((x | ((x & 0x7f7f7f7fu) + 0x5f5f5f5fu)) & 0x80808080u) bad |= ST_FORMAT;
-        wsum += __builtin_amdgcn_sad_u8(x, 0u, 0u);
-      }
-    } else if (o < g.off_s) {  // outliers: O -> -O
+    for (int u = 0; u < kNegUnroll; ++u) {
+      const uint64_t k = k0 + uint64_t(u) * stride;
+      if (k >= nfull) continue;
+      const uint64_t o = 16 * k;
+      uint32_t wd[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+      if (o >= g.off_p || o + 16 <= g.off_w) {
+        // header or payload: copy
+      } else if (o < g.off_o) {  // widths (and the padding after them)
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if (o + 4 * q < o_end) wd[q] = 0u - wd[q];
-    } else {  // signs
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const uint64_t b0 = o + 4 * q;
-        if (b0 >= s_end) continue;
-        const uint64_t seg = (b0 - g.off_s) / 4;
-        const uint64_t blk = (seg >> g.spb_log2);
-        if (p.c[g.off_w + blk] == 0) continue;  // constant block: no signs
-        uint32_t cnt = 32;
-        if (blk == g.nb - 1) {
-          uint64_t blen;
-          cnt = seg_count(g, blk, uint32_t(seg & (g.spb - 1)), blen);
+        for (int q = 0; q < 4; ++q) {
+          const uint64_t b0 = o + 4 * q;
+          uint32_t x = wd[q];
+          if (b0 >= w_end) continue;
+          if (b0 + 4 > w_end) x &= 0xffffffffu >> (8 * (b0 + 4 - w_end));
+          if ((x | ((x & 0x7f7f7f7fu) + 0x5f5f5f5fu)) & 0x80808080u) bad |= ST_FORMAT;
+          wsum += __builtin_amdgcn_sad_u8(x, 0u, 0u);
         }
-        if (cnt == 0) continue;
-        const uint32_t be = cnt == 32 ? 0xffffffffu : ~(0xffffffffu >> cnt);
-        wd[q] ^= bswap32(be);
+      } else if (o < g.off_s) {  // outliers: O -> -O
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (o + 4 * q < o_end) wd[q] = 0u - wd[q];
+      } else {  // signs
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const uint64_t b0 = o + 4 * q;
+          if (b0 >= s_end) continue;
+          const uint64_t seg = (b0 - g.off_s) / 4;
+          const uint64_t blk = (seg >> g.spb_log2);
+          if (((wq[u] >> (8 * (blk & 3))) & 0xffu) == 0) continue;  // constant block: no signs
+          uint32_t cnt = 32;
+          if (blk == g.nb - 1) {
+            uint64_t blen;
+            cnt = seg_count(g, blk, uint32_t(seg & (g.spb - 1)), blen);
+          }
+          if (cnt == 0) continue;
+          const uint32_t be = cnt == 32 ? 0xffffffffu : ~(0xffffffffu >> cnt);
+          wd[q] ^= bswap32(be);
+        }
       }
+      dst[k] = make_uint4(wd[0], wd[1], wd[2], wd[3]);
     }
-    dst[k] = make_uint4(wd[0], wd[1], wd[2], wd[3]);
   }
+  // the last partial chunk (payload words only): one thread
+  if (!err && blockIdx.x == 0 && tid == 0)
+    for (uint64_t b = 16 * nfull; b < g.total_bytes; b += 4)
+      *reinterpret_cast<uint32_t*>(p.out + b) = *reinterpret_cast<const uint32_t*>(p.c + b);
   latch(p.s, bad);
   wsum = wave_sum(wsum);
   if ((tid & 63) == 0 && wsum)
