@@ -140,7 +140,7 @@ inline __host__ __device__ uint64_t batch_tiles(const Layout& g) {
 
 // Occupancy-derived persistent grid sizes, filled at context creation.
 struct Grids {
-  int compress, decode, add, mul, negate, widths, f32;
+  int compress, decode, reduce, add, mul, negate, widths, f32;
 };
 
 // ---- launchers (kernels.hip) ----------------------------------------------

@@ -1233,14 +1233,24 @@ __device__ __forceinline__ void meta_b(const Layout& g, const uint32_t* S, const
 // wait on each other.  The loop is software-pipelined: widths, outliers and
 // offsets are loaded two tiles ahead, sign words and the first payload words
 // one tile ahead, so memory latency overlaps the current tile's arithmetic.
+// Workgroup size of the decoders: decompression keeps 32 output values per
+// lane (about 200 VGPRs), so 256 threads; the reductions fit 128 VGPRs and
+// run one 1024-thread workgroup per CU (the same 16 waves per CU as four
+// 256-thread groups, with a quarter of the end-of-kernel atomics).
+constexpr int kReduceThreads = 1024;
+__host__ __device__ constexpr int decode_threads(int mode) {
+  return mode == kDecompress ? kThreads : kReduceThreads;
+}
+
 template <int MODE>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(decode_threads(MODE))
     __attribute__((amdgpu_waves_per_eu(MODE == kDecompress ? 1 : 4))) k_decode(DecodeParams p) {
+  constexpr int NT = decode_threads(MODE);
   // per-wave payload staging, reused by decompression to transpose its output
-  __shared__ __align__(16) uint32_t s_pay[kThreads / 64][kWaveWords + 4];
+  __shared__ __align__(16) uint32_t s_pay[NT / 64][kWaveWords + 4];
   __shared__ uint32_t s_flag;
-  __shared__ int64_t s_rs[kThreads / 64];
-  __shared__ uint64_t s_rl[kThreads / 64], s_rh[kThreads / 64];
+  __shared__ int64_t s_rs[NT / 64];
+  __shared__ uint64_t s_rl[NT / 64], s_rh[NT / 64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   Layout g;
   uint32_t err = read_header(p.c, p.c_bytes, g);
@@ -1257,8 +1267,8 @@ __global__ void __launch_bounds__(kThreads)
   int64_t acc_s = 0;
   uint64_t acc_ql = 0, acc_qh = 0;
   uint32_t bad = 0;
-  const uint64_t stride = uint64_t(gridDim.x) * (kThreads / 64);
-  const uint64_t wt0 = uint64_t(blockIdx.x) * (kThreads / 64) + wave;
+  const uint64_t stride = uint64_t(gridDim.x) * (NT / 64);
+  const uint64_t wt0 = uint64_t(blockIdx.x) * (NT / 64) + wave;
   MetaA a1, a2;
   MetaB b0;
   if (wt0 < nwt) {
@@ -1400,7 +1410,7 @@ __global__ void __launch_bounds__(kThreads)
   latch(p.s, bad);
   double value = 0.0;
   if (MODE != kDecompress) {
-    wg_sum_s_q(acc_s, acc_ql, acc_qh, s_rs, s_rl, s_rh);
+    wg_sum_s_q<NT>(acc_s, acc_ql, acc_qh, s_rs, s_rl, s_rh);
     if (tid == 0) {
       atomicAdd(reinterpret_cast<unsigned long long*>(&p.s.acc[A_S]), (unsigned long long)acc_s);
       if (MODE == kVariance) {
@@ -2059,9 +2069,9 @@ hipError_t launch_reduce(const Scratch& s, const Grids& gr, const uint8_t* c, ui
   if (e != hipSuccess) return e;
   DecodeParams p{c, c_bytes, nullptr, 0, s, res};
   if (variance)
-    hipLaunchKernelGGL(k_decode<kVariance>, dim3(gr.decode), dim3(kThreads), 0, st, p);
+    hipLaunchKernelGGL(k_decode<kVariance>, dim3(gr.reduce), dim3(kReduceThreads), 0, st, p);
   else
-    hipLaunchKernelGGL(k_decode<kMean>, dim3(gr.decode), dim3(kThreads), 0, st, p);
+    hipLaunchKernelGGL(k_decode<kMean>, dim3(gr.reduce), dim3(kReduceThreads), 0, st, p);
   return hipGetLastError();
 }
 
@@ -2130,16 +2140,20 @@ int batch_max_grid(int num_cus) {
 hipError_t query_grids(Grids& gr, int num_cus) {
   int c = 0, d = 0, a = 0, m = 0;
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&c, k_compress<1, kCompressThreads>, kCompressThreads, 0);
-  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&d, k_decode<kVariance>, kThreads, 0);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&d, k_decode<kDecompress>, kThreads, 0);
+  int r = 0;
+  if (e == hipSuccess)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&r, k_decode<kMean>, kReduceThreads, 0);
   if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_add<kAddThreads>, kAddThreads, 0);
   if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&m, k_mul<kMulThreads>, kMulThreads, 0);
   if (e != hipSuccess) return e;
   auto clampg = [&](int occ) { return num_cus * (occ < 1 ? 1 : occ); };
   gr.compress = clampg(c);
   gr.decode = clampg(d);
+  gr.reduce = clampg(r);
   gr.add = clampg(a);
   gr.mul = clampg(m);
-  gr.negate = num_cus * 8;
+  gr.negate = num_cus;  // one workgroup per CU: fewer end-of-kernel atomics, measured fastest
   gr.widths = num_cus;
   gr.f32 = num_cus * 4;
   return hipSuccess;
