@@ -1632,9 +1632,26 @@ __global__ void __launch_bounds__(NT) k_add(AddParams p) {
     uint32_t ma[32];
     {
       const uint32_t* sp = &s_pay[1 + off_a];
-      const uint32_t ww = wa ? wa : 1u;  // width 0: fields read, then dropped
+      const uint32_t rs = 32u - wa;
+      uint32_t pa = 0;
+      if (wa == 0) {
 #pragma unroll
-      for (int j = 0; j < 32; ++j) ma[j] = wa ? field(sp, uint32_t(j), ww) : 0u;
+        for (int j = 0; j < 32; ++j) ma[j] = 0;
+      } else if (wa <= 16) {  // two whole fields per 32-bit window
+#pragma unroll
+        for (int j = 0; j < 32; j += 2) {
+          const uint32_t win = window_at(sp, pa);
+          pa += 2 * wa;
+          ma[j] = win >> rs;
+          ma[j + 1] = (win << wa) >> rs;
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < 32; ++j) {
+          ma[j] = field_at(sp, pa, rs);
+          pa += wa;
+        }
+      }
     }
     const uint32_t* spb = &s_pay[tw_a + 2 + off_b];
     if (!both) {
