@@ -36,7 +36,7 @@
  *   run concurrently (use one stream per context, or one context per stream).
  * - Streams are self-describing: the 64-byte header carries n, the block size
  *   and the error bound, so decoders take no shape arguments.
- * - Limits: 1 <= n <= 2^32 - 1 elements; block size 32, 64 or 128; the error
+ * - Limits: 1 <= n <= 2^32 - 1 elements; block size 32, 64, 128 or 256; the error
  *   bound `eb` is absolute, finite and > 0; quantization bins must lie in
  *   [-(2^31 - 1), 2^31 - 1].  Float input pointers must be 16-byte aligned;
  *   stream pointers 16-byte aligned.
@@ -228,7 +228,7 @@ typedef struct hoszp_field {
   const float* d_x;  /* n float32 values, 16-byte aligned, caller-owned */
   uint64_t n;        /* 1 <= n <= 2^32 - 1 */
   double eb;         /* absolute error bound, finite and > 0 */
-  uint32_t block;    /* 32, 64, 128, or 0 = chosen by the autotuner */
+  uint32_t block;    /* 32, 64, 128, 256, or 0 = chosen by the autotuner (from 32, 64, 128) */
   uint32_t reserved; /* must be 0 */
   void* d_out;       /* output stream, 16-byte aligned, caller-owned */
   uint64_t out_cap;  /* >= hoszp_compress_bound(n, block); with block 0 the

@@ -137,7 +137,10 @@ typedef struct {
 
 static uint64_t round16(uint64_t x) { return (x + 15u) / 16u * 16u; }
 
-static int block_ok(uint32_t block) { return block == 32 || block == 64 || block == 128; }
+#define MAX_BLOCK 256 /* largest block size accepted */
+static int block_ok(uint32_t block) {
+  return block == 32 || block == 64 || block == 128 || block == 256;
+}
 
 static void place_sections(layout* g) {
   g->nb = (g->n + g->block - 1) / g->block;
@@ -249,8 +252,8 @@ int hoszp_ref_quantize(const float* x, uint64_t n, double eb, int32_t* q) {
 static unsigned encode_block(uint8_t* out, const layout* g, uint64_t b, int32_t outlier,
                              const int64_t* d, uint64_t bitpos) {
   const uint32_t L = g->block;
-  uint32_t mag[128];
-  unsigned neg[128];
+  uint32_t mag[MAX_BLOCK];
+  unsigned neg[MAX_BLOCK];
   uint32_t biggest = 0;
   for (uint32_t k = 0; k < L; ++k) {
     neg[k] = d[k] < 0 ? 1u : 0u;
@@ -302,7 +305,7 @@ int hoszp_ref_encode_bins(const int32_t* q, uint64_t n, double eb, uint32_t bloc
   g.eb = eb;
   place_sections(&g);
   memset(out, 0, bound);
-  int64_t d[128];
+  int64_t d[MAX_BLOCK];
   uint64_t bits = 0;
   for (uint64_t b = 0; b < g.nb; ++b) {
     uint64_t first = b * block;
@@ -356,7 +359,7 @@ typedef int (*block_visitor)(void* user, uint64_t b, uint32_t len, int32_t outli
                              const int64_t* d);
 
 static int for_each_block(const uint8_t* c, const layout* g, block_visitor visit, void* user) {
-  int64_t d[128];
+  int64_t d[MAX_BLOCK];
   uint64_t bits = 0;
   for (uint64_t b = 0; b < g->nb; ++b) {
     int32_t outlier;
@@ -464,7 +467,7 @@ int hoszp_ref_add(const uint8_t* a, size_t a_bytes, const uint8_t* b, size_t b_b
   layout g = ga;
   uint8_t* z = (uint8_t*)calloc(bound, 1); /* output may alias an input */
   if (z == NULL) return REF_ERR_ARG;
-  int64_t da[128], db[128], dz[128];
+  int64_t da[MAX_BLOCK], db[MAX_BLOCK], dz[MAX_BLOCK];
   uint64_t bits_a = 0, bits_b = 0, bits_z = 0;
   for (uint64_t k = 0; k < g.nb && rc == REF_OK; ++k) {
     int32_t oa, ob;

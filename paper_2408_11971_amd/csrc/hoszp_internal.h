@@ -56,13 +56,15 @@ struct Layout {
 };
 
 __host__ __device__ inline uint64_t round16(uint64_t x) { return (x + 15u) & ~uint64_t(15); }
-__host__ __device__ inline bool block_ok(uint32_t L) { return L == 32 || L == 64 || L == 128; }
+__host__ __device__ inline bool block_ok(uint32_t L) {
+  return L == 32 || L == 64 || L == 128 || L == 256;
+}
 
 __host__ __device__ inline void place(Layout& g, uint64_t n, uint32_t L, double eb) {
   g.n = n;
   g.L = L;
   g.spb = L / 32;
-  g.spb_log2 = L == 32 ? 0u : (L == 64 ? 1u : 2u);
+  g.spb_log2 = L == 32 ? 0u : (L == 64 ? 1u : (L == 128 ? 2u : 3u));
   g.eb = eb;
   g.nb = (n + L - 1) / L;
   g.nseg = g.nb * g.spb;

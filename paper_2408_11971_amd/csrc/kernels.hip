@@ -617,8 +617,10 @@ __device__ __forceinline__ uint32_t widths_of_16(const uint8_t* c, const Layout&
     } else if (nbk == 8) {
       const uint2 v = *reinterpret_cast<const uint2*>(W + b0);
       q[0] = v.x, q[1] = v.y;
-    } else {
+    } else if (nbk == 4) {
       q[0] = *reinterpret_cast<const uint32_t*>(W + b0);
+    } else {  // block 256: two blocks, b0 even
+      q[0] = *reinterpret_cast<const uint16_t*>(W + b0);
     }
   } else {
     for (uint32_t k = 0; k < uint32_t(have); ++k) q[k >> 2] |= uint32_t(W[b0 + k]) << (8 * (k & 3));
@@ -1001,8 +1003,12 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch(BatchParams p) {
         words = compress_tile<2, true, kBatchThreads>(fd.x, fd.out, g, fd.eb, fd.inv2e, tile, p.st + fd.tile0,
                                        epoch, sh, bad, sums, &p.ctrl[B_TICKET], next);
         break;
-      default:
+      case 4:
         words = compress_tile<4, true, kBatchThreads>(fd.x, fd.out, g, fd.eb, fd.inv2e, tile, p.st + fd.tile0,
+                                       epoch, sh, bad, sums, &p.ctrl[B_TICKET], next);
+        break;
+      default:
+        words = compress_tile<8, true, kBatchThreads>(fd.x, fd.out, g, fd.eb, fd.inv2e, tile, p.st + fd.tile0,
                                        epoch, sh, bad, sums, &p.ctrl[B_TICKET], next);
         break;
     }
@@ -2063,6 +2069,7 @@ hipError_t launch_compress(const Scratch& s, const Grids& gr, const float* x, co
     case 32: hipLaunchKernelGGL((k_compress<1, kCompressThreads>), dim3(uint32_t(grid)), dim3(kCompressThreads), 0, st, p); break;
     case 64: hipLaunchKernelGGL((k_compress<2, kCompressThreads>), dim3(uint32_t(grid)), dim3(kCompressThreads), 0, st, p); break;
     case 128: hipLaunchKernelGGL((k_compress<4, kCompressThreads>), dim3(uint32_t(grid)), dim3(kCompressThreads), 0, st, p); break;
+    case 256: hipLaunchKernelGGL((k_compress<8, kCompressThreads>), dim3(uint32_t(grid)), dim3(kCompressThreads), 0, st, p); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

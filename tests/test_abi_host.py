@@ -40,7 +40,7 @@ def test_result_record_is_64_bytes():
     assert hz.result_struct_size() == 64 == hz.RESULT_BYTES
 
 
-@pytest.mark.parametrize("L", [32, 64, 128])
+@pytest.mark.parametrize("L", [32, 64, 128, 256])
 def test_compress_bound_matches_oracle(lib, L):
     for n in [1, 2, 31, 32, 33, 1000, 8191, 8192, 8193, 123457, 1 << 20, 2**32 - 1]:
         assert hz.compress_bound(n, L) == ref.bound(n, L)
@@ -49,11 +49,11 @@ def test_compress_bound_matches_oracle(lib, L):
 def test_compress_bound_rejects_bad_args(lib):
     assert hz.compress_bound(0, 32) == 0
     assert hz.compress_bound(10, 16) == 0
-    assert hz.compress_bound(10, 256) == 0
+    assert hz.compress_bound(10, 512) == 0
     assert hz.compress_bound(2**32, 32) == 0
 
 
-@pytest.mark.parametrize("L", [32, 64, 128])
+@pytest.mark.parametrize("L", [32, 64, 128, 256])
 def test_parse_header_matches_oracle(lib, L):
     x = np.random.default_rng(L).normal(0, 1, 5000).astype(np.float32)
     c = ref.compress(x, 0.01, L)

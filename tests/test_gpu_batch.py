@@ -107,7 +107,7 @@ def test_batch_autotuned_blocks_and_grid(dev):
 
 def test_batch_matches_single_field_ops(dev):
     print("case batch vs single ops", flush=True)
-    fields = make_fields(13, [8193, 100000, 33, 77777], [32, 64, 128, 32])
+    fields = make_fields(13, [8193, 100000, 33, 77777], [32, 64, 128, 256])
     b, gx, outs = run_batch(fields, dev)
     b.launch()
     res = b.results()

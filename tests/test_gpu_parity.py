@@ -19,7 +19,7 @@ import paper_2408_11971_amd as hz  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
-BLOCKS = [32, 64, 128]
+BLOCKS = [32, 64, 128, 256]
 REL = 1e-12
 
 

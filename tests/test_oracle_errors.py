@@ -46,7 +46,7 @@ def test_bad_arguments():
     x = np.zeros(10, dtype=np.float32)
     for eb in (0.0, -1.0, np.inf, np.nan):
         assert code_of(ref.compress, x, eb, 32) == ref.ERR_ARG
-    for L in (0, 16, 48, 256, 33):
+    for L in (0, 16, 48, 512, 33):
         assert code_of(ref.compress, x, 0.1, L) == ref.ERR_ARG
     assert ref.bound(0, 32) == 0
     assert ref.bound(10, 48) == 0

@@ -14,7 +14,7 @@ from hypothesis import HealthCheck, given, settings, strategies as st
 import spec_fraction as spec
 from oracle import ref
 
-BLOCKS = [32, 64, 128]
+BLOCKS = [32, 64, 128, 256]
 
 small_floats = st.floats(min_value=-1000.0, max_value=1000.0, allow_nan=False,
                          allow_infinity=False, width=32)

@@ -5,7 +5,7 @@ import pytest
 from oracle import ref
 import synth
 
-BLOCKS = [32, 64, 128]
+BLOCKS = [32, 64, 128, 256]
 
 
 def seeded(n, seed, scale=10.0):

@@ -49,7 +49,7 @@ def sign_list(sbytes, n):
     return [(int(sbytes[k // 8]) >> (7 - k % 8)) & 1 for k in range(n)]
 
 
-@pytest.mark.parametrize("L", [32, 64, 128])
+@pytest.mark.parametrize("L", [32, 64, 128, 256])
 def test_compress_matches_paper_example(L):
     q = ref.quantize(X, EPS)
     assert q.tolist() == ints("bins")
