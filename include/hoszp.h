@@ -228,7 +228,7 @@ typedef struct hoszp_field {
   const float* d_x;  /* n float32 values, 16-byte aligned, caller-owned */
   uint64_t n;        /* 1 <= n <= 2^32 - 1 */
   double eb;         /* absolute error bound, finite and > 0 */
-  uint32_t block;    /* 32, 64, 128, 256, or 0 = chosen by the autotuner (from 32, 64, 128) */
+  uint32_t block;    /* 32, 64, 128, or 0 = chosen by the autotuner (a batch takes no 256) */
   uint32_t reserved; /* must be 0 */
   void* d_out;       /* output stream, 16-byte aligned, caller-owned */
   uint64_t out_cap;  /* >= hoszp_compress_bound(n, block); with block 0 the

@@ -490,7 +490,9 @@ uint64_t field_cap_needed(const hoszp_field& f) {
 int check_field(const hoszp_field& f) {
   if (!f.d_x || !f.d_out || !aligned(f.d_x, 16) || !aligned(f.d_out, 16) || f.reserved) return HOSZP_ERR_ARG;
   if (f.n == 0 || f.n > hz::kMaxN || !(f.eb > 0.0) || !isfinite(f.eb)) return HOSZP_ERR_ARG;
-  if (f.block && !hz::block_ok(f.block)) return HOSZP_ERR_ARG;
+  // batches take blocks up to 128: a fourth tile body in the batch kernel
+  // measurably slows the common block sizes
+  if (f.block && (!hz::block_ok(f.block) || f.block > 128)) return HOSZP_ERR_ARG;
   if (f.out_cap < field_cap_needed(f)) return HOSZP_ERR_CAPACITY;
   return HOSZP_OK;
 }

@@ -1003,12 +1003,8 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch(BatchParams p) {
         words = compress_tile<2, true, kBatchThreads>(fd.x, fd.out, g, fd.eb, fd.inv2e, tile, p.st + fd.tile0,
                                        epoch, sh, bad, sums, &p.ctrl[B_TICKET], next);
         break;
-      case 4:
+      default:  // 4: batches take blocks up to 128 (checked when planned)
         words = compress_tile<4, true, kBatchThreads>(fd.x, fd.out, g, fd.eb, fd.inv2e, tile, p.st + fd.tile0,
-                                       epoch, sh, bad, sums, &p.ctrl[B_TICKET], next);
-        break;
-      default:
-        words = compress_tile<8, true, kBatchThreads>(fd.x, fd.out, g, fd.eb, fd.inv2e, tile, p.st + fd.tile0,
                                        epoch, sh, bad, sums, &p.ctrl[B_TICKET], next);
         break;
     }

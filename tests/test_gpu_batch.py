@@ -107,7 +107,7 @@ def test_batch_autotuned_blocks_and_grid(dev):
 
 def test_batch_matches_single_field_ops(dev):
     print("case batch vs single ops", flush=True)
-    fields = make_fields(13, [8193, 100000, 33, 77777], [32, 64, 128, 256])
+    fields = make_fields(13, [8193, 100000, 33, 77777], [32, 64, 128, 32])
     b, gx, outs = run_batch(fields, dev)
     b.launch()
     res = b.results()
@@ -173,9 +173,11 @@ def test_batch_rejects_bad_fields(dev):
     with pytest.raises(hz.HoszpError) as e:
         hz.Batch([(x, -1.0, 32, out)])
     assert e.value.code == hz.ERR_ARG
-    with pytest.raises(hz.HoszpError) as e:
-        hz.Batch([(x, 0.1, 48, out)])
-    assert e.value.code == hz.ERR_ARG
+    for bad_block in (48, 256):  # 256 is a valid stream block, but not in a batch
+        with pytest.raises(hz.HoszpError) as e:
+            hz.Batch([(x, 0.1, bad_block, torch.zeros(hz.batch_out_cap(100, 256), dtype=torch.uint8,
+                                                        device=dev))])
+        assert e.value.code == hz.ERR_ARG
 
 
 def test_batch_full_size_sampled(dev):
