@@ -726,6 +726,12 @@ struct BinSums {
     ql += sq;
     qh += ql < sq ? 1u : 0u;
   }
+  // a segment's sums: s32 = sum of its bins, sq = sum of their squares
+  __device__ __forceinline__ void add_segment(int32_t s32, uint64_t sq) {
+    s += s32;
+    ql += sq;
+    qh += ql < sq ? 1u : 0u;
+  }
 };
 
 // Quantize 32 values, form Lorenzo deltas, split signs and magnitudes.
@@ -737,6 +743,11 @@ __device__ __forceinline__ void quantize_segment(const float* v, uint32_t cnt, b
                                                  uint32_t* mag, uint32_t& sgn, uint32_t& mx,
                                                  int32_t& outlier, uint32_t& bad, BinSums& sums) {
   int32_t qp = prev;
+  // STATS: the segment's bins are summed in 32 bits and their squares in 64
+  // (exact while every |bin| < 2^26: 32 of them sum below 2^31 and 2^57), else
+  // the sums are redone one bin at a time from the deltas below
+  int32_t ss = 0, qlo = 0, qhi = 0;
+  uint64_t sq = 0;
 #pragma unroll
   for (int j = 0; j < 32; ++j) {
     const float xv = v[j];
@@ -745,7 +756,12 @@ __device__ __forceinline__ void quantize_segment(const float* v, uint32_t cnt, b
     const int32_t q = ok ? int32_t(f) : 0;
     const bool valid = FULL || uint32_t(j) < cnt;
     if (valid && !ok) bad |= isfinite(xv) ? ST_RANGE : ST_NONFINITE;
-    if (STATS && valid) sums.add(q);
+    if (STATS && valid) {
+      ss += q;
+      sq += uint64_t(int64_t(q) * int64_t(q));
+      qlo = min(qlo, q);
+      qhi = max(qhi, q);
+    }
     bool neg = false;
     uint32_t m = 0;
     if (j == 0 && first_seg) {
@@ -761,6 +777,23 @@ __device__ __forceinline__ void quantize_segment(const float* v, uint32_t cnt, b
     sgn |= uint32_t(neg) << (31 - j);
     mx = max(mx, m);
     qp = q;
+  }
+  if (STATS) {
+    constexpr int32_t kSmall = 1 << 26;
+    if (qlo > -kSmall && qhi < kSmall) {
+      sums.add_segment(ss, sq);
+    } else {  // rebuild the bins from the outlier or prev and the deltas
+      int32_t q = prev;
+      for (int j = 0; j < int(cnt); ++j) {
+        if (j == 0 && first_seg) {
+          q = outlier;
+        } else {
+          const uint32_t m = mag[j];
+          q = int32_t(((sgn >> (31 - j)) & 1u) ? uint32_t(q) - m : uint32_t(q) + m);
+        }
+        sums.add(q);
+      }
+    }
   }
 }
 

@@ -105,6 +105,22 @@ def test_batch_autotuned_blocks_and_grid(dev):
     assert b.info()["grid"] >= 1
 
 
+def test_batch_sums_of_large_bins(dev):
+    """Segments whose bins reach 2^26 or more sum them one by one (the 32/64-bit
+    per-segment sums would not be exact): mean and variance still equal the
+    oracle's, beside fields of small bins and ragged lengths."""
+    print("case batch large bins", flush=True)
+    rng = np.random.default_rng(21)
+    big = rng.uniform(-2.0**30, 2.0**30, 70001).astype(np.float32)
+    mixed = rng.normal(0.0, 1.0, 50000).astype(np.float32)
+    mixed[1000:1100] = 2.0**29  # a run of large bins inside small ones
+    fields = [(big, 0.5, 32), (mixed, 0.5, 64), (big[:33333], 0.5, 128),
+              (rng.normal(0.0, 1.0, 8193).astype(np.float32), 1e-3, 32)]
+    b, _, outs = run_batch(fields, dev)
+    b.launch()
+    check_against_oracle(fields, b.results(), outs)
+
+
 def test_batch_matches_single_field_ops(dev):
     print("case batch vs single ops", flush=True)
     fields = make_fields(13, [8193, 100000, 33, 77777], [32, 64, 128, 32])
