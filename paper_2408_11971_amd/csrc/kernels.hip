@@ -1269,9 +1269,10 @@ __device__ __forceinline__ void meta_b(const Layout& g, const uint32_t* S, const
 // offsets are loaded two tiles ahead, sign words and the first payload words
 // one tile ahead, so memory latency overlaps the current tile's arithmetic.
 // Workgroup size of the decoders: decompression keeps 32 output values per
-// lane (about 200 VGPRs), so 256 threads; the reductions fit 128 VGPRs and
-// run one 1024-thread workgroup per CU (the same 16 waves per CU as four
-// 256-thread groups, with a quarter of the end-of-kernel atomics).
+// lane (at most 168 VGPRs, 3 waves per SIMD), so 256 threads; the reductions
+// fit 128 VGPRs and run one 1024-thread workgroup per CU (the same 16 waves
+// per CU as four 256-thread groups, with a quarter of the end-of-kernel
+// atomics).
 constexpr int kReduceThreads = 1024;
 __host__ __device__ constexpr int decode_threads(int mode) {
   return mode == kDecompress ? kThreads : kReduceThreads;
@@ -1279,7 +1280,7 @@ __host__ __device__ constexpr int decode_threads(int mode) {
 
 template <int MODE>
 __global__ void __launch_bounds__(decode_threads(MODE))
-    __attribute__((amdgpu_waves_per_eu(MODE == kDecompress ? 1 : 4))) k_decode(DecodeParams p) {
+    __attribute__((amdgpu_waves_per_eu(MODE == kDecompress ? 3 : 4))) k_decode(DecodeParams p) {
   constexpr int NT = decode_threads(MODE);
   // per-wave payload staging, reused by decompression to transpose its output
   __shared__ __align__(16) uint32_t s_pay[NT / 64][kWaveWords + 4];
@@ -1373,8 +1374,9 @@ __global__ void __launch_bounds__(decode_threads(MODE))
         E2 = uint64_t(e2);
         D = d1;
       } else {
-        D = w <= 16 ? prefix_fast<true>(sp, w, sw, sub == 0, keep32)
-                    : prefix_fast<false>(sp, w, sw, sub == 0, keep32);
+        // one field per window here: the paired read costs the registers
+        // that keep decompression at 3 waves per SIMD
+        D = prefix_fast<false>(sp, w, sw, sub == 0, keep32);
       }
     } else if (cnt > 0) {
       D = decode_generic<MODE == kDecompress, int32_t>(sp, sw, w, sub, cnt, E, E2w, keep32);
