@@ -15,7 +15,9 @@
 //     workgroups.
 // Payload words are staged in LDS as big-endian values (one byte swap per
 // word), so a w-bit field at bit p of a segment is one funnel shift
-// (v_alignbit) of two neighbouring LDS words.
+// (v_alignbit) of two neighbouring LDS words.  Wave-level sums and minima are
+// ds_swizzle butterflies and wave scans DPP row shifts and broadcasts, so no
+// lane-index registers stay live in the kernels' loops.
 //
 // Every operation ends in one kernel whose last workgroup to finish writes
 // the caller's result record and returns the context's counters to zero, so
@@ -30,13 +32,12 @@ constexpr double kBinMaxD = 2147483647.0;
 constexpr uint64_t kLbAgg = 1, kLbInc = 2;
 constexpr uint64_t kLbValMask = (uint64_t(1) << 34) - 1;
 constexpr uint32_t kNone = 0xffffffffu;
-constexpr uint32_t kEpochLimit = 1u << 28;
-// Workgroup size (= segments per look-back tile) of single-field compression:
-// larger tiles halve the serial look-back steps.
+constexpr uint32_t kEpochLimit = 1u << 28;  // look-back epochs are 28-bit, never 0
+// Workgroup size (= segments per look-back tile) of the single-field
+// encoders: larger tiles halve the serial look-back steps.
 constexpr int kCompressThreads = 1024;
 constexpr int kMulThreads = 1024;
 constexpr int kAddThreads = 1024;
-  // look-back epochs are 28-bit, never 0
 
 enum { kMean = 0, kVariance = 1, kDecompress = 2 };
 // context counters (Scratch::ctrl) and accumulators (Scratch::acc)
@@ -1583,9 +1584,10 @@ struct AddParams {
 };
 
 // Element-wise addition, one tile of NT segments per workgroup.  The two
-// operands' payloads are staged one after the other in the same LDS buffer:
-// A's magnitudes are held in registers while B's payload replaces A's, so the
-// workgroup needs one tile of LDS, not two.
+// operands' payloads share one tile's LDS buffer: both at once when their
+// words fit (B right after A), else one after the other (A's magnitudes held
+// in registers while B's payload replaces A's), so the workgroup never needs
+// two tiles of LDS.
 template <int NT>
 __global__ void __launch_bounds__(NT) k_add(AddParams p) {
   __shared__ uint32_t s_pay[NT * 32 + 2];
