@@ -1710,16 +1710,9 @@ __global__ void __launch_bounds__(NT) k_add(AddParams p) {
       const uint32_t rb = 32u - wb;
       uint32_t pb = 0;
       int32_t dsum = 0;
-#pragma unroll
-      for (int j = 0; j < 32; ++j) {
-        const int32_t sa = int32_t(swa << j) >> 31;
-        int32_t d = (int32_t(ma[j]) ^ sa) - sa;
-        if (wb) {
-          const int32_t m = int32_t(field_at(spb, pb, rb));
-          const int32_t s = int32_t(swb << j) >> 31;
-          d += (m ^ s) - s;
-        }
-        pb += wb;
+      auto step = [&](int j, int32_t fb) {  // fb: B's magnitude of slot j
+        const int32_t sa = int32_t(swa << j) >> 31, sb = int32_t(swb << j) >> 31;
+        int32_t d = ((int32_t(ma[j]) ^ sa) - sa) + ((fb ^ sb) - sb);
         if (j == 0 && sub == 0) d = 0;
         const uint32_t neg = uint32_t(d) >> 31;
         const uint32_t m = neg ? 0u - uint32_t(d) : uint32_t(d);
@@ -1727,6 +1720,23 @@ __global__ void __launch_bounds__(NT) k_add(AddParams p) {
         sgn |= neg << (31 - j);
         mx = max(mx, m);
         dsum += d;
+      };
+      if (__all(wb >= 1 && wb <= 16)) {  // wave-uniform: two B fields per window
+#pragma unroll
+        for (int j = 0; j < 32; j += 2) {
+          const uint32_t win = window_at(spb, pb);
+          pb += 2 * wb;
+          step(j, int32_t(win >> rb));
+          step(j + 1, int32_t((win << wb) >> rb));
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < 32; ++j) {
+          int32_t fb = 0;
+          if (wb) fb = int32_t(field_at(spb, pb, rb));
+          pb += wb;
+          step(j, fb);
+        }
       }
       D = dsum;
     } else {
