@@ -162,7 +162,8 @@ int hoszp_negate_async(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, void* d_
  * deltas added, then widths, signs and bits re-derived.  Both operands must
  * have the same n, block size and bitwise-equal eb (else MISMATCH); a sum bin
  * outside the bin range gives RANGE.  The output is the canonical stream of
- * the summed bins.  d_out must not overlap the inputs. */
+ * the summed bins.  d_out must not overlap the inputs: a byte range
+ * [d_out, d_out + out_cap) that meets either input gives ARG. */
 int hoszp_add(hoszp_ctx* ctx, const void* d_a, size_t a_bytes, const void* d_b, size_t b_bytes,
               void* d_out, size_t out_cap, size_t* out_bytes, void* stream);
 int hoszp_add_async(hoszp_ctx* ctx, const void* d_a, size_t a_bytes, const void* d_b,
@@ -171,11 +172,21 @@ int hoszp_add_async(hoszp_ctx* ctx, const void* d_a, size_t a_bytes, const void*
 
 /* Scalar multiplication (Sec. V-A-4, workflow 3): bins decoded, replaced by
  * floor(s * bin + 1/2) computed exactly, then re-encoded.  s must be finite;
- * a result outside the bin range gives RANGE.  d_out must not overlap d_c. */
+ * a result outside the bin range gives RANGE.  d_out must not overlap d_c
+ * ([d_out, d_out + out_cap) meeting [d_c, d_c + c_bytes) gives ARG). */
 int hoszp_mul(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, double s, void* d_out,
               size_t out_cap, size_t* out_bytes, void* stream);
 int hoszp_mul_async(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, double s, void* d_out,
                     size_t out_cap, hoszp_result* d_res, void* stream);
+
+/* The scalar-multiplication rounding rule alone, on the host (Sec. V-A-4):
+ * h_out[i] = floor(s * h_q[i] + 1/2) in exact arithmetic, computed by the
+ * same function the kernels use.  h_q and h_out are n int32 values in host
+ * memory (caller-owned, may be the same array).  Returns ARG for a
+ * non-finite s or a NULL array with n > 0, RANGE when some result leaves
+ * [-(2^31-1), 2^31-1] (that h_out[i] is then 0; the others are still
+ * written), else OK.  Needs no device. */
+int hoszp_mul_bins(double s, const int32_t* h_q, int32_t* h_out, uint64_t n);
 
 /* Mean (Sec. V-B-1): ((double)S / n) * 2 eb with S the exact int64 sum of
  * the bins. */

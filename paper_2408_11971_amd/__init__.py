@@ -109,6 +109,7 @@ _SIGNATURES = {
     "hoszp_add_async": (_INT, [_VP, _VP, _SZ, _VP, _SZ, _VP, _SZ, _VP, _VP]),
     "hoszp_mul": (_INT, [_VP, _VP, _SZ, _DBL, _VP, _SZ, ctypes.POINTER(_SZ), _VP]),
     "hoszp_mul_async": (_INT, [_VP, _VP, _SZ, _DBL, _VP, _SZ, _VP, _VP]),
+    "hoszp_mul_bins": (_INT, [_DBL, _VP, _VP, _U64]),
     "hoszp_mean": (_INT, [_VP, _VP, _SZ, ctypes.POINTER(_DBL), _VP]),
     "hoszp_mean_async": (_INT, [_VP, _VP, _SZ, _VP, _VP]),
     "hoszp_variance": (_INT, [_VP, _VP, _SZ, ctypes.POINTER(_DBL), _VP]),
@@ -178,6 +179,18 @@ def parse_header(header: bytes) -> dict:
 
 def status_code(mask: int) -> int:
     return _lib().hoszp_status_code(mask)
+
+
+def mul_bins(s: float, q):
+    """floor(s q + 1/2) exactly for an int32 numpy array q, by the rounding
+    function the scalar-multiplication kernel uses (host code, no device).
+    Returns (code, results); out-of-range results are 0 with code ERR_RANGE."""
+    import numpy as np
+
+    q = np.ascontiguousarray(q, dtype=np.int32)
+    out = np.empty_like(q)
+    rc = _lib().hoszp_mul_bins(float(s), _VP(q.ctypes.data), _VP(out.ctypes.data), q.size)
+    return rc, out
 
 
 # ---------------------------------------------------------------- contexts
@@ -582,8 +595,3 @@ def fill_request(rec, op, a, b=None, scalar=0.0, path=PATH_HOMOMORPHIC, tag=0, i
 def result_struct_size() -> int:
     return ctypes.sizeof(Result)
 
-
-def pack_header_fields(n, block, eb, payload, total):
-    """Header bytes for tests of the host-side parser."""
-    nb = (n + block - 1) // block
-    return struct.pack("<4sHHIIQdQQQQ", b"HOSZ", 1, 0, block, 0, n, eb, nb, payload, total, 0)

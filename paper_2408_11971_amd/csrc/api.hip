@@ -59,6 +59,14 @@ class DeviceScope {
 
 inline bool aligned(const void* p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
+// Whether the byte ranges [a, a + na) and [b, b + nb) share a byte.  Add and
+// mul write payload words of a tile before later tiles have read theirs, so
+// an output that overlaps an input would corrupt the result.
+inline bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const uintptr_t pa = reinterpret_cast<uintptr_t>(a), pb = reinterpret_cast<uintptr_t>(b);
+  return na && nb && pa < pb + nb && pb < pa + na;
+}
+
 // Next look-back generation.  Status words carry the generation, so they never
 // need clearing -- except once every 2^28 - 1 calls when the counter wraps.
 int next_epoch(hoszp_ctx* ctx, hipStream_t st, uint32_t* epoch) {
@@ -97,8 +105,8 @@ bool stream_args_ok(hoszp_ctx* ctx, const void* d_c, hoszp_result* d_res) {
   return ctx && d_c && d_res && aligned(d_c, 16) && aligned(d_res, 8);
 }
 
-// Classify the scalar s = m 2^e (|m| < 2^53) as the exact definition does:
-// e >= 0 makes every non-zero bin overflow, e < -100 makes every result 0.
+// Classify the scalar s = m 2^e (|m| < 2^53): e < -100 (|s| < 2^-48) makes
+// every result 0, and the kernels then multiply by an exact 0.
 hz::MulScalar mul_split(double s) {
   hz::MulScalar k{s, 0, 0};
   int e2 = 0;
@@ -106,7 +114,6 @@ hz::MulScalar mul_split(double s) {
   const int64_t m = int64_t(ldexp(frac, 53));
   const int e = e2 - 53;
   if (m == 0 || -e > 100) k.zero = 1;  // |s q| < 2^-16: every result rounds to 0
-  else if (e >= 0) k.big = 1;
   return k;
 }
 
@@ -333,7 +340,8 @@ int hoszp_add_async(hoszp_ctx* ctx, const void* d_a, size_t a_bytes, const void*
                     size_t b_bytes, void* d_out, size_t out_cap, hoszp_result* d_res,
                     void* stream) {
   if (!stream_args_ok(ctx, d_a, d_res) || !d_b || !aligned(d_b, 16) || !d_out ||
-      !aligned(d_out, 16))
+      !aligned(d_out, 16) || overlap(d_out, out_cap, d_a, a_bytes) ||
+      overlap(d_out, out_cap, d_b, b_bytes))
     return HOSZP_ERR_ARG;
   DeviceScope scope(ctx->device);
   if (!scope.ok()) return HOSZP_ERR_DEVICE;
@@ -359,7 +367,8 @@ int hoszp_add(hoszp_ctx* ctx, const void* d_a, size_t a_bytes, const void* d_b, 
 
 int hoszp_mul_async(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, double s, void* d_out,
                     size_t out_cap, hoszp_result* d_res, void* stream) {
-  if (!stream_args_ok(ctx, d_c, d_res) || !d_out || !aligned(d_out, 16) || !isfinite(s))
+  if (!stream_args_ok(ctx, d_c, d_res) || !d_out || !aligned(d_out, 16) || !isfinite(s) ||
+      overlap(d_out, out_cap, d_c, c_bytes))
     return HOSZP_ERR_ARG;
   DeviceScope scope(ctx->device);
   if (!scope.ok()) return HOSZP_ERR_DEVICE;
@@ -380,6 +389,19 @@ int hoszp_mul(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, double s, void* d
   hoszp_result r;
   rc = hoszp_result_wait(ctx, ctx->d_res, &r, stream);
   if (rc == HOSZP_OK) *out_bytes = size_t(r.out_bytes);
+  return rc;
+}
+
+int hoszp_mul_bins(double s, const int32_t* h_q, int32_t* h_out, uint64_t n) {
+  if ((n && (!h_q || !h_out)) || !isfinite(s)) return HOSZP_ERR_ARG;
+  const double sc = mul_split(s).zero ? 0.0 : s;
+  int rc = HOSZP_OK;
+  for (uint64_t i = 0; i < n; ++i) {
+    const double f = hz::mul_round(sc, double(h_q[i]));
+    const bool ok = fabs(f) <= double(hz::kBinMax);
+    h_out[i] = ok ? int32_t(f) : 0;
+    if (!ok) rc = HOSZP_ERR_RANGE;
+  }
   return rc;
 }
 

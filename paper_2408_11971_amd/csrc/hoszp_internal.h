@@ -108,9 +108,36 @@ struct Scratch {
 // Scalar multiplier, classified on the host (see mul_split()).
 struct MulScalar {
   double s;     // the scalar
-  int32_t big;  // 1 when |s| >= 2^52: any non-zero bin overflows
   int32_t zero; // 1 when |s q| < 2^-16 for every int32 q: every result is 0
+  int32_t pad;
 };
+
+// floor(s q + 1/2) in exact arithmetic (scalar multiplication of Sec. V-A,
+// rounding half up), returned as a double that is exact whenever the result
+// can be a bin; |result| > 2^31 - 1 (or infinite) means out of range.
+// Requires s finite and s = 0 or |s| >= 2^-48 (smaller multipliers give 0 for
+// every int32 q and are replaced by 0 on the host), so nothing underflows.
+//   y = fl(s q) and e = fma(s, q, -y) give s q = y + e exactly, |e| <= ulp(y)/2.
+//   h = rint(y) is an integer and r = y - h is exact with |r| <= 1/2: for
+//   |y| >= 1/2 both are multiples of ulp(y) <= 1 and |r| <= 2^52 ulp(y); for
+//   |y| < 1/2, h = 0 and r = y.
+//   s q + 1/2 = h + (r + e + 1/2).  Unless r = +-1/2 exactly, r is at least
+//   ulp(y) away from both (a multiple of ulp(y) when |y| >= 1/2; the largest
+//   double below 1/2 is 1/2 - ulp(y) when |y| < 1/2), so r + e + 1/2 lies in
+//   (0, 1) and the result is h.  At r = 1/2 it is h + 1 when e >= 0, else h;
+//   at r = -1/2 it is h - 1 when e < 0, else h.
+//   For |y| >= 2^52, r = 0 and |h| is far outside the bin range, as is the
+//   exact result; overflow gives an infinite h.
+// Shared by the kernels and the host function hoszp_mul_bins.
+__host__ __device__ inline double mul_round(double s, double q) {
+  const double y = s * q;
+  const double e = fma(s, q, -y);
+  const double h = rint(y);
+  const double r = y - h;
+  const double up = (r == 0.5 && e >= 0.0) ? 1.0 : 0.0;
+  const double dn = (r == -0.5 && e < 0.0) ? 1.0 : 0.0;
+  return (h + up) - dn;
+}
 
 // One field of a batched compress, as the kernel sees it.
 struct BatchField {

@@ -1815,23 +1815,9 @@ struct MulParams {
   hoszp_result* res;
 };
 
-// floor(s q + 1/2) exactly, in binary64, without branches: y = fl(s q) and
-// err = fma(s, q, -y) give s q = y + err exactly (the FMA two-product
-// error-free transformation; no underflow since s is 0 or |s| >= 2^-48 and
-// q != 0 or y = 0); while |y| <= 2^52, z = y + 1/2 and g = z - floor(z) are
-// exact, and err only moves the floor by one when it crosses an integer,
-// which the two exact comparisons detect.  Beyond that |floor(z)| is far
-// outside the bin range (infinite or NaN when s q overflows), and the one
-// range check flags it.
+// One scaled bin (mul_round) with the range check of the output bin.
 __device__ __forceinline__ int32_t scaled_bin(int32_t q, double s, uint32_t& bad) {
-  const double qd = double(q);
-  const double y = s * qd;
-  const double err = fma(s, qd, -y);
-  const double z = y + 0.5;
-  double f = floor(z);
-  const double g = z - f;
-  f += err < -g ? -1.0 : 0.0;
-  f += err >= 1.0 - g ? 1.0 : 0.0;
+  const double f = mul_round(s, double(q));
   const bool ok = fabs(f) <= kBinMaxD;
   bad |= ok ? 0u : uint32_t(ST_RANGE);
   return ok ? int32_t(f) : 0;

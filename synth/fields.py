@@ -95,7 +95,7 @@ def grf_3d(n: int = 512, seed: int = 3, device=None):
     k = _radial_k((n, n, n))
     with np.errstate(divide="ignore"):
         filt = np.where(k > 0, k ** (-11.0 / 6.0), 0.0)
-    field = np.fft.irfftn(spec * filt, s=(n, n, n))
+    field = np.fft.irfftn(spec * filt, s=(n, n, n), axes=(0, 1, 2))
     field = (field - field.mean()) / field.std()
     return field.astype(np.float32)
 

@@ -104,7 +104,7 @@ def test_fullsize_compress_reductions_decompress(fields, rel):
         assert np.array_equal(x[i:j], ref.decompress(ref.compress(a[i:j], eb, L))), f"[{i},{j})"
 
 
-@pytest.mark.parametrize("rel", [1e-3])
+@pytest.mark.parametrize("rel", [1e-2, 1e-3, 1e-4])
 def test_fullsize_homomorphic_ops(fields, rel):
     print(f"case fullsize ops rel={rel}", flush=True)
     A, B, a, b = fields
@@ -112,10 +112,47 @@ def test_fullsize_homomorphic_ops(fields, rel):
     eb = rel * synth.value_range(A)
     ca = hz.compress(A, eb, L)
     cb = hz.compress(B, eb, L)
-    slices = sample_slices(n, 7)
+    slices = sample_slices(n, 7 + int(-np.log10(rel)))
     check_slices(hz.add(ca, cb).cpu().numpy(), n, slices,
                  lambda i, j: ref.add(ref.compress(a[i:j], eb, L), ref.compress(b[i:j], eb, L)))
     check_slices(hz.mul(ca, 3.14).cpu().numpy(), n, slices,
                  lambda i, j: ref.mul(ref.compress(a[i:j], eb, L), 3.14))
     check_slices(hz.negate(cb).cpu().numpy(), n, slices,
                  lambda i, j: ref.negate(ref.compress(b[i:j], eb, L)))
+
+
+# ------------------------------------------- 1800 x 3600 climate-like steps
+
+@pytest.fixture(scope="module")
+def climate():
+    steps = [s.ravel() for s in synth.climate_steps(nsteps=3)]
+    return steps
+
+
+@pytest.mark.parametrize("block", [32, 64, 128])
+def test_fullsize_climate_steps(climate, block):
+    """Three whole 1800x3600 steps (6.48M elements each, 2 % exact zeros) at
+    eb = 1e-4 of each step's range: every stream, decoded field and reduction
+    of the climate sweep compared with the oracle in full."""
+    print(f"case fullsize climate block={block}", flush=True)
+    dev = torch.device("cuda:0")
+    s = np.random.default_rng(9).uniform(-2.0, 2.0, 3)
+    prev = None
+    for t, x in enumerate(climate):
+        eb = synth.rel_eb(x, 1e-4)
+        xc = ref.compress(x, eb, block)
+        c = hz.compress(torch.from_numpy(x).to(dev), eb, block)
+        assert np.array_equal(c.cpu().numpy(), xc), f"compress step {t}"
+        assert np.array_equal(hz.decompress(c).cpu().numpy(), ref.decompress(xc)), f"step {t}"
+        m, v = ref.mean(xc), ref.variance(xc)
+        assert abs(hz.mean(c) - m) <= 1e-12 * abs(m)
+        assert abs(hz.variance(c) - v) <= 1e-12 * abs(v)
+        assert np.array_equal(hz.negate(c).cpu().numpy(), ref.negate(xc)), f"negate step {t}"
+        assert np.array_equal(hz.mul(c, float(s[t])).cpu().numpy(), ref.mul(xc, float(s[t]))), \
+            f"mul step {t}"
+        if prev is not None:
+            # pairwise step add: both operands at this step's eb (add needs equal eb)
+            pc = ref.compress(prev, eb, block)
+            got = hz.add(hz.compress(torch.from_numpy(prev).to(dev), eb, block), c)
+            assert np.array_equal(got.cpu().numpy(), ref.add(pc, xc)), f"add steps {t-1}+{t}"
+        prev = x

@@ -192,6 +192,31 @@ def test_bad_arguments(dev):
     assert err_of(hz.mul, c, math.inf) == hz.ERR_ARG
 
 
+def test_output_overlapping_an_input_is_rejected(dev):
+    """add and mul refuse an output range that shares bytes with an input
+    (a tile's output words could overwrite input words later tiles read);
+    nothing is launched, so the buffer is left as it was."""
+    x = synth.sinusoid_1d(40000, 3)
+    xc = ref.compress(x, 1e-3, 32)
+    cap = hz.compress_bound(x.size, 32)
+    buf = torch.zeros(2 * cap + 4096, dtype=torch.uint8, device=dev)
+    buf[:xc.size] = gpu(xc, dev)
+    a = buf[:xc.size]
+    before = host(buf).copy()
+    for off in (0, 16, xc.size - 16):
+        out = buf[off:off + cap]
+        assert err_of(hz.mul, a, 2.0, out=out) == hz.ERR_ARG
+        assert err_of(hz.add, a, a, out=out) == hz.ERR_ARG
+    other = gpu(xc, dev)
+    assert err_of(hz.add, other, a, out=buf[64:64 + cap]) == hz.ERR_ARG
+    assert np.array_equal(host(buf), before)
+    # disjoint ranges of the same allocation are fine
+    start = (xc.size + 15) // 16 * 16
+    out = buf[start:start + cap]
+    assert np.array_equal(host(hz.mul(a, 2.0, out=out)), ref.mul(xc, 2.0))
+    assert np.array_equal(host(hz.add(a, other, out=out)), ref.add(xc, xc))
+
+
 def corruptions(c):
     out = []
     for off, val in [(0, ord("X")), (4, 2), (8, 48), (32, int(c[32]) + 1), (64, 33),
@@ -305,7 +330,9 @@ def test_async_chain_matches_sync(dev):
 
 
 @pytest.mark.parametrize("s", [0.5, 1.5, -2.5, 1.0 / 3.0, 0.1, 3 * 2.0**-20, 1e-5, 123.456,
-                               -0.7499999999999999, 2.0**51 * 1.5, 2.0**-101])
+                               -0.7499999999999999, 2.0**51 * 1.5, 2.0**-101, 1.1, 0.55,
+                               0.49999999999999994, 0.24999999999999997,
+                               -0.49999999999999994])
 def test_mul_rounding_ties(dev, s):
     """Integer-valued fields at eb = 1/2 (bins equal the values): scalars that
     put s q exactly on, or one ulp beside, half-integers must round like the
@@ -314,6 +341,7 @@ def test_mul_rounding_ties(dev, s):
     rng = np.random.default_rng(17)
     q = rng.integers(-200000, 200001, 40000)
     q[::7] = rng.integers(-3, 4, q[::7].size)
+    q[5::11] = rng.choice([465, -465, 930, -930, 150000, -150000, 1, 2, 4], q[5::11].size)
     x = q.astype(np.float32)
     xc = ref.compress(x, 0.5, 32)
     c = hz.compress(gpu(x, dev), 0.5, 32)
@@ -326,3 +354,30 @@ def test_mul_rounding_ties(dev, s):
         assert g.value.code == e.code
         return
     assert np.array_equal(host(hz.mul(c, s)), want), f"mul by {s!r}"
+
+
+def test_mul_exact_rounding_classes(dev):
+    """Scalar multiplication on the GPU on every near-tie class of
+    floor(s q + 1/2) (s q within a few ulps of a half-integer, including
+    y = 1/2 - 2^-54 and y = 2^k - 1/2 + ulp(y)): the stream equals the
+    oracle's, and the decoded bins equal exact rational arithmetic."""
+    from mul_cases import exact_mul_bins, tie_cases
+
+    rng = np.random.default_rng(31)
+    cases = tie_cases()
+    print(f"case mul tie classes: {len(cases)} scalars", flush=True)
+    for i, (s, q) in enumerate(cases):
+        fill = rng.integers(-50, 51, 97).astype(np.int32)
+        field = np.concatenate([fill[: i % 40], q, fill, q[::-1]]).astype(np.int32)
+        xc = ref.encode_bins(field, 0.5, 32)
+        c = gpu(xc, dev)
+        want = exact_mul_bins(s, field)
+        if any(w is None for w in want):
+            with pytest.raises(hz.HoszpError) as g:
+                hz.mul(c, s)
+            assert g.value.code == hz.ERR_RANGE, s
+            continue
+        got = host(hz.mul(c, s))
+        assert np.array_equal(got, ref.mul(xc, s)), f"mul stream differs for s={s!r}"
+        assert np.array_equal(ref.decode_bins(got).astype(np.int64),
+                              np.array(want, dtype=np.int64)), f"mul bins differ for s={s!r}"
