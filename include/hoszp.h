@@ -74,6 +74,7 @@ extern "C" {
 #define HOSZP_ERR_CAPACITY 6  /* output buffer too small */
 #define HOSZP_ERR_DEVICE 7    /* a HIP runtime call failed */
 #define HOSZP_ERR_NOMEM 8     /* device or pinned allocation failed */
+#define HOSZP_ERR_LIMIT 9     /* input larger than an allocation-free entry point allows */
 
 /* Outcome of an asynchronous call, written by the GPU into caller-owned
  * device memory (64 bytes, 8-byte aligned).
@@ -400,6 +401,31 @@ int hoszp_server_stats_get(const hoszp_server* s, hoszp_server_stats* out);
 /* Wait for every running query, then free everything (outputs still held by
  * completions are freed with the pool). */
 int hoszp_server_destroy(hoszp_server* s);
+
+/* ---- allocation-free compression ---------------------------------------
+ *
+ * For callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * compression as hoszp_compress_async (identical stream, same result record)
+ * with no context.  Its scratch (tile ticket, counters, one look-back status
+ * word per 32768-element tile) is a fixed 66 KB array in device global
+ * memory that every device holds from its first call until the process ends;
+ * the first call on a device looks up that array's address (nothing is
+ * allocated, launched or synchronized then).  Each call clears the part of
+ * the array it uses with a small kernel on `stream`, then enqueues the
+ * compression; it never allocates, frees or synchronizes, so it can be
+ * captured.  The device is the calling thread's current HIP device.
+ *
+ * Limits: 1 <= n <= HOSZP_NOALLOC_MAX_N (2^28 elements = 1 GiB of float32);
+ * a larger n returns HOSZP_ERR_LIMIT and enqueues nothing.  Other arguments
+ * and errors as hoszp_compress_async.  Every call on one device shares that
+ * device's array: calls that overlap in time on one device (two streams, two
+ * threads) race and give undefined results; calls in one stream are ordered
+ * and safe.  Concurrent use of hoszp_compress_async with a context is
+ * unaffected. */
+#define HOSZP_NOALLOC_MAX_N (1ull << 28)
+int hoszp_compress_noalloc(const float* d_x, uint64_t n, double eb, uint32_t block, void* d_out,
+                           size_t out_cap, hoszp_result* d_res, void* stream);
 
 /* Block until `stream` is idle and return the code of a result record that
  * an async call filled (also copying it to *h_out when h_out is not NULL). */

@@ -16,7 +16,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhoszp.so")
 
 OK, ERR_ARG, ERR_NONFINITE, ERR_RANGE, ERR_FORMAT, ERR_MISMATCH, ERR_CAPACITY, ERR_DEVICE, \
-    ERR_NOMEM = range(9)
+    ERR_NOMEM, ERR_LIMIT = range(10)
+NOALLOC_MAX_N = 1 << 28
 RESULT_BYTES = 64
 
 
@@ -120,6 +121,7 @@ _SIGNATURES = {
     "hoszp_f32_mean_async": (_INT, [_VP, _VP, _U64, _VP, _VP]),
     "hoszp_f32_variance_async": (_INT, [_VP, _VP, _U64, _VP, _VP]),
     "hoszp_result_wait": (_INT, [_VP, _VP, ctypes.POINTER(Result), _VP]),
+    "hoszp_compress_noalloc": (_INT, [_VP, _U64, _DBL, _U32, _VP, _SZ, _VP, _VP]),
     "hoszp_batch_create": (_INT, [_VP, ctypes.POINTER(Field), _U64, _U32, _VP, ctypes.POINTER(_VP),
                                   ctypes.POINTER(_U64)]),
     "hoszp_batch_launch": (_INT, [_VP, _VP]),
@@ -357,6 +359,15 @@ def compress_async(x, eb, block, out, res, ctx=None, stream=None):
     _check(_lib().hoszp_compress_async(ctx.handle, _ptr(x), x.numel(), float(eb), block,
                                        _ptr(out), _nbytes(out), _ptr(res), _stream(stream)),
            "compress_async")
+
+
+def compress_noalloc(x, eb, block, out, res, stream=None):
+    """hoszp_compress_noalloc: compress float32 tensor x into `out` with no
+    context and no device allocation (the library's fixed scratch array of
+    the current device); the outcome lands in the device record `res`."""
+    _check(_lib().hoszp_compress_noalloc(_ptr(x), x.numel(), float(eb), block, _ptr(out),
+                                         _nbytes(out), _ptr(res), _stream(stream)),
+           "compress_noalloc")
 
 
 def decompress_async(c, out, res, ctx=None, stream=None, c_bytes=None):

@@ -140,6 +140,7 @@ const char* hoszp_strerror(int code) {
     case HOSZP_ERR_CAPACITY: return "output buffer too small";
     case HOSZP_ERR_DEVICE: return "HIP runtime error";
     case HOSZP_ERR_NOMEM: return "out of memory";
+    case HOSZP_ERR_LIMIT: return "input larger than the allocation-free entry point allows (n <= 2^28)";
     default: return "unknown status";
   }
 }
