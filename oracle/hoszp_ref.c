@@ -20,6 +20,12 @@
  *   Sec. V-B-1  mean           2 eps * (sum q) / N
  *   Sec. V-B-2  variance       population variance of the bins times (2 eps)^2
  *   Sec. V-C-1  element add    O_A + O_B and signed P_A + P_B, then BF
+ *   Sec. V-A    scalar add/sub O +- q_s, q_s the scalar's bin by Eq. 3
+ *   Sec. V-B    std            sqrt of the variance
+ *   Sec. V-B    block means    2 eps * (sum of a block's q) / its length
+ *   Sec. V-C    element sub    bins q_A - q_B, then LZ -> BF
+ *   Sec. V-C    Hadamard       bins floor(2 eps q_A q_B + 1/2), then LZ -> BF
+ *   Sec. V-D    covariance     (2 eps_A)(2 eps_B) (n sum q_A q_B - S_A S_B) / n^2
  *
  * Readings of points the paper leaves open (each is listed with its reason in
  * the design notes of the repository):
@@ -39,6 +45,12 @@
  *     non-constant blocks.
  *   - Scalar multiplication uses the unquantized scalar and rounds half up,
  *     which equals re-quantizing s * (2 eps q) with Eq. 3.
+ *   - Scalar addition and subtraction use the scalar's bin by Eq. 3 (the
+ *     bin printed in the paper's example, 33 for 0.67 at eps 0.01, is one
+ *     below what Eq. 3 gives, 34).  The Hadamard product re-quantizes the
+ *     product of the decoded values at the operands' eps with half-up
+ *     rounding, as scalar multiplication does.  Covariance and the block
+ *     means divide exact integer sums, as the mean and variance do.
  *
  * Stream layout (all integers little-endian):
  *   header, 64 bytes:  "HOSZ" | u16 version=1 | u16 flags=0 | u32 block |
@@ -631,4 +643,253 @@ int hoszp_ref_variance(const uint8_t* c, size_t c_bytes, double* var) {
   const double two_eb = 2.0 * g.eb;
   *var = (((double)m / (double)g.n) / (double)g.n) * (two_eb * two_eb);
   return REF_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Sec. V-A: scalar addition and subtraction (workflow 1)               */
+/* ------------------------------------------------------------------ */
+
+/* Quantization bin of a scalar by Eq. 3, evaluated like every element. */
+static int scalar_bin(double s, double eb, int64_t* qs) {
+  if (!isfinite(s)) return REF_ERR_ARG;
+  const double two_eb = 2.0 * eb;
+  const double inv = 1.0 / two_eb;
+  double sum = s + eb; /* two separately rounded operations, as Eq. 3 */
+  double t = sum * inv;
+  double bin = floor(t);
+  if (!(bin >= -(double)BIN_MAX && bin <= (double)BIN_MAX)) return REF_ERR_RANGE;
+  *qs = (int64_t)bin;
+  return REF_OK;
+}
+
+typedef struct {
+  int64_t delta;
+} shift_check;
+
+/* every shifted bin q + delta must stay in the bin range */
+static int check_shifted(void* user, uint64_t b, uint32_t len, int32_t outlier, const int64_t* d) {
+  (void)b;
+  const shift_check* sc = (const shift_check*)user;
+  int64_t v = outlier;
+  for (uint32_t k = 0; k < len; ++k) {
+    if (k > 0) v += d[k];
+    if (v < -BIN_MAX || v > BIN_MAX) return REF_ERR_FORMAT;
+    if (v + sc->delta < -BIN_MAX || v + sc->delta > BIN_MAX) return REF_ERR_RANGE;
+  }
+  return REF_OK;
+}
+
+/* Add `delta` to every bin by adding it to every outlier; widths, signs and
+ * magnitudes are copied unchanged (the deltas do not change). */
+static int shift_outliers(const uint8_t* c, size_t c_bytes, double s, int sign, uint8_t* out,
+                          size_t out_cap, size_t* out_bytes) {
+  layout g;
+  int rc = read_layout(c, c_bytes, &g);
+  if (rc) return rc;
+  if (out == NULL || out_bytes == NULL) return REF_ERR_ARG;
+  int64_t qs = 0;
+  rc = scalar_bin(s, g.eb, &qs);
+  if (rc) return rc;
+  if (out_cap < g.total_bytes) return REF_ERR_CAPACITY;
+  shift_check sc = {sign * qs};
+  rc = for_each_block(c, &g, check_shifted, &sc);
+  if (rc) return rc;
+  if (out != c) memmove(out, c, (size_t)g.total_bytes);
+  for (uint64_t b = 0; b < g.nb; ++b) {
+    int64_t o = (int64_t)(int32_t)get_u32(out + g.off_o + 4u * b);
+    put_u32(out + g.off_o + 4u * b, (uint32_t)(int32_t)(o + sc.delta));
+  }
+  *out_bytes = (size_t)g.total_bytes;
+  return REF_OK;
+}
+
+int hoszp_ref_scalar_add(const uint8_t* c, size_t c_bytes, double s, uint8_t* out,
+                         size_t out_cap, size_t* out_bytes) {
+  return shift_outliers(c, c_bytes, s, 1, out, out_cap, out_bytes);
+}
+
+int hoszp_ref_scalar_sub(const uint8_t* c, size_t c_bytes, double s, uint8_t* out,
+                         size_t out_cap, size_t* out_bytes) {
+  return shift_outliers(c, c_bytes, s, -1, out, out_cap, out_bytes);
+}
+
+/* ------------------------------------------------------------------ */
+/* Sec. V-B: standard deviation                                         */
+/* ------------------------------------------------------------------ */
+
+int hoszp_ref_std(const uint8_t* c, size_t c_bytes, double* std) {
+  double var = 0.0;
+  int rc = hoszp_ref_variance(c, c_bytes, &var);
+  if (rc) return rc;
+  if (std == NULL) return REF_ERR_ARG;
+  *std = sqrt(var);
+  return REF_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Bivariate operations (Sec. V-C, V-D): both operands decoded to bins   */
+/* ------------------------------------------------------------------ */
+
+/* Bins of both operands; `need_eb` additionally requires equal error bounds. */
+static int decode_pair(const uint8_t* a, size_t a_bytes, const uint8_t* b, size_t b_bytes,
+                       int need_eb, layout* ga, layout* gb, int32_t** qa, int32_t** qb) {
+  int rc = read_layout(a, a_bytes, ga);
+  if (rc) return rc;
+  rc = read_layout(b, b_bytes, gb);
+  if (rc) return rc;
+  if (need_eb ? !same_shape(ga, gb) : (ga->n != gb->n || ga->block != gb->block))
+    return REF_ERR_MISMATCH;
+  *qa = (int32_t*)malloc(ga->n * sizeof(int32_t));
+  *qb = (int32_t*)malloc(gb->n * sizeof(int32_t));
+  if (*qa == NULL || *qb == NULL) {
+    free(*qa);
+    free(*qb);
+    *qa = *qb = NULL;
+    return REF_ERR_ARG;
+  }
+  rc = hoszp_ref_decode_bins(a, a_bytes, *qa, ga->n);
+  if (rc == REF_OK) rc = hoszp_ref_decode_bins(b, b_bytes, *qb, gb->n);
+  if (rc) {
+    free(*qa);
+    free(*qb);
+    *qa = *qb = NULL;
+  }
+  return rc;
+}
+
+/* Sec. V-C: element-wise subtraction, bins q_A - q_B re-encoded. */
+int hoszp_ref_sub(const uint8_t* a, size_t a_bytes, const uint8_t* b, size_t b_bytes,
+                  uint8_t* out, size_t out_cap, size_t* out_bytes) {
+  if (out == NULL || out_bytes == NULL) return REF_ERR_ARG;
+  layout ga, gb;
+  int32_t *qa, *qb;
+  int rc = decode_pair(a, a_bytes, b, b_bytes, 1, &ga, &gb, &qa, &qb);
+  if (rc) return rc;
+  if (out_cap < hoszp_ref_bound(ga.n, ga.block)) rc = REF_ERR_CAPACITY;
+  for (uint64_t i = 0; i < ga.n && rc == REF_OK; ++i) {
+    int64_t v = (int64_t)qa[i] - (int64_t)qb[i];
+    if (v < -BIN_MAX || v > BIN_MAX) rc = REF_ERR_RANGE;
+    else qa[i] = (int32_t)v;
+  }
+  if (rc == REF_OK) rc = hoszp_ref_encode_bins(qa, ga.n, ga.eb, ga.block, out, out_cap, out_bytes);
+  free(qa);
+  free(qb);
+  return rc;
+}
+
+/* floor(2 eps * p + 1/2) in exact arithmetic for an integer p (|p| < 2^62):
+ * 2 eps = m * 2^e with an integer m (|m| < 2^53). */
+static int exact_scaled_product(double two_eb, i128 p, int64_t* result) {
+  int e2;
+  double frac = frexp(two_eb, &e2);
+  int64_t m = (int64_t)ldexp(frac, 53);
+  int e = e2 - 53;
+  i128 t = (i128)m * p; /* |t| < 2^115 */
+  i128 r;
+  if (t == 0) {
+    r = 0;
+  } else if (e >= 0) {
+    if (e > 40) return REF_ERR_RANGE;
+    r = t * ((i128)1 << e);
+  } else if (-e > 120) {
+    r = 0; /* |t 2^e| < 2^-5: rounds to 0 */
+  } else {
+    int sh = -e;
+    i128 rnd = (i128)1 << (sh - 1); /* + 1/2 */
+    i128 num = t + rnd;
+    i128 quo = num / ((i128)1 << sh);
+    if (num < 0 && quo * ((i128)1 << sh) != num) quo -= 1; /* floor */
+    r = quo;
+  }
+  if (r < -(i128)BIN_MAX || r > (i128)BIN_MAX) return REF_ERR_RANGE;
+  *result = (int64_t)r;
+  return REF_OK;
+}
+
+/* Sec. V-C: Hadamard product.  The decoded values multiply to
+ * (2 eps)^2 q_A q_B; re-quantized at eps with half-up rounding (as scalar
+ * multiplication) that is floor(2 eps q_A q_B + 1/2). */
+int hoszp_ref_hadamard(const uint8_t* a, size_t a_bytes, const uint8_t* b, size_t b_bytes,
+                       uint8_t* out, size_t out_cap, size_t* out_bytes) {
+  if (out == NULL || out_bytes == NULL) return REF_ERR_ARG;
+  layout ga, gb;
+  int32_t *qa, *qb;
+  int rc = decode_pair(a, a_bytes, b, b_bytes, 1, &ga, &gb, &qa, &qb);
+  if (rc) return rc;
+  if (out_cap < hoszp_ref_bound(ga.n, ga.block)) rc = REF_ERR_CAPACITY;
+  const double two_eb = 2.0 * ga.eb;
+  for (uint64_t i = 0; i < ga.n && rc == REF_OK; ++i) {
+    int64_t r;
+    rc = exact_scaled_product(two_eb, (i128)qa[i] * (i128)qb[i], &r);
+    if (rc == REF_OK) qa[i] = (int32_t)r;
+  }
+  if (rc == REF_OK) rc = hoszp_ref_encode_bins(qa, ga.n, ga.eb, ga.block, out, out_cap, out_bytes);
+  free(qa);
+  free(qb);
+  return rc;
+}
+
+/* Sec. V-D: population covariance of the two decoded fields,
+ * ((double)(n P - S_A S_B) / n / n) * (2 eps_A) (2 eps_B) with P = sum q_A q_B
+ * and S = sum q, all exact.  The operands need equal n and block size; their
+ * error bounds may differ. */
+int hoszp_ref_covariance(const uint8_t* a, size_t a_bytes, const uint8_t* b, size_t b_bytes,
+                         double* cov) {
+  if (cov == NULL) return REF_ERR_ARG;
+  layout ga, gb;
+  int32_t *qa, *qb;
+  int rc = decode_pair(a, a_bytes, b, b_bytes, 0, &ga, &gb, &qa, &qb);
+  if (rc) return rc;
+  i128 sa = 0, sb = 0, p = 0;
+  for (uint64_t i = 0; i < ga.n; ++i) {
+    sa += qa[i];
+    sb += qb[i];
+    p += (i128)qa[i] * (i128)qb[i];
+  }
+  /* |n P - S_A S_B| <= n sqrt(Q_A Q_B) < 2^126 (Cauchy-Schwarz) */
+  i128 m = (i128)ga.n * p - sa * sb;
+  *cov = (((double)m / (double)ga.n) / (double)ga.n) * ((2.0 * ga.eb) * (2.0 * gb.eb));
+  free(qa);
+  free(qb);
+  return REF_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Sec. V-B: block-wise means and constant blocks (Table VI)            */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+  double* means;
+  double two_eb;
+  uint64_t constant;
+  const uint8_t* widths;
+} block_mean_sink;
+
+static int store_block_mean(void* user, uint64_t b, uint32_t len, int32_t outlier,
+                            const int64_t* d) {
+  block_mean_sink* s = (block_mean_sink*)user;
+  int64_t v = outlier, sum = 0;
+  for (uint32_t k = 0; k < len; ++k) {
+    if (k > 0) v += d[k];
+    if (v < -BIN_MAX || v > BIN_MAX) return REF_ERR_FORMAT;
+    sum += v;
+  }
+  s->means[b] = ((double)sum / (double)len) * s->two_eb;
+  if (s->widths[b] == 0) s->constant += 1; /* width 0: every bin equals the outlier */
+  return REF_OK;
+}
+
+/* means[b] = ((double)S_b / len_b) * 2 eps for every block b (S_b = exact sum
+ * of the block's bins); *constant_blocks = blocks of width 0. */
+int hoszp_ref_block_means(const uint8_t* c, size_t c_bytes, double* means, uint64_t nb_cap,
+                          uint64_t* constant_blocks) {
+  layout g;
+  int rc = read_layout(c, c_bytes, &g);
+  if (rc) return rc;
+  if (means == NULL || constant_blocks == NULL) return REF_ERR_ARG;
+  if (nb_cap < g.nb) return REF_ERR_CAPACITY;
+  block_mean_sink s = {means, 2.0 * g.eb, 0, c + g.off_w};
+  rc = for_each_block(c, &g, store_block_mean, &s);
+  if (rc == REF_OK) *constant_blocks = s.constant;
+  return rc;
 }

@@ -83,6 +83,36 @@ int hoszp_ref_mean(const uint8_t* c, size_t c_bytes, double* mean);
  * ((double)(n Q - S^2) / n / n) * ((2 eb) * (2 eb)). */
 int hoszp_ref_variance(const uint8_t* c, size_t c_bytes, double* var);
 
+/* Homomorphic scalar addition / subtraction (Sec. V-A; workflow 1): the
+ * scalar's bin q_s by Eq. 3 is added to (subtracted from) every outlier;
+ * widths, signs and magnitudes are copied.  RANGE if q_s or any result bin
+ * leaves the bin range; out may equal c. */
+int hoszp_ref_scalar_add(const uint8_t* c, size_t c_bytes, double s, uint8_t* out,
+                         size_t out_cap, size_t* out_bytes);
+int hoszp_ref_scalar_sub(const uint8_t* c, size_t c_bytes, double s, uint8_t* out,
+                         size_t out_cap, size_t* out_bytes);
+
+/* Standard deviation (Sec. V-B): sqrt of the population variance. */
+int hoszp_ref_std(const uint8_t* c, size_t c_bytes, double* std);
+
+/* Element-wise subtraction (Sec. V-C): bins q_A - q_B, canonical stream. */
+int hoszp_ref_sub(const uint8_t* a, size_t a_bytes, const uint8_t* b, size_t b_bytes,
+                  uint8_t* out, size_t out_cap, size_t* out_bytes);
+
+/* Hadamard product (Sec. V-C): bins floor(2 eps q_A q_B + 1/2), exact. */
+int hoszp_ref_hadamard(const uint8_t* a, size_t a_bytes, const uint8_t* b, size_t b_bytes,
+                       uint8_t* out, size_t out_cap, size_t* out_bytes);
+
+/* Population covariance (Sec. V-D) from exact integer sums; the operands
+ * need equal n and block size (their error bounds may differ). */
+int hoszp_ref_covariance(const uint8_t* a, size_t a_bytes, const uint8_t* b, size_t b_bytes,
+                         double* cov);
+
+/* Block-wise means (Sec. V-B): means[b] = ((double)S_b / len_b) * (2 eps),
+ * and the number of constant (width 0) blocks. */
+int hoszp_ref_block_means(const uint8_t* c, size_t c_bytes, double* means, uint64_t nb_cap,
+                          uint64_t* constant_blocks);
+
 #ifdef __cplusplus
 }
 #endif

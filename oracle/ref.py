@@ -54,6 +54,13 @@ def lib():
             "hoszp_ref_sums": (ctypes.c_int, [u8p, sz, P(ctypes.c_int64), P(u64), P(u64)]),
             "hoszp_ref_mean": (ctypes.c_int, [u8p, sz, P(dbl)]),
             "hoszp_ref_variance": (ctypes.c_int, [u8p, sz, P(dbl)]),
+            "hoszp_ref_scalar_add": (ctypes.c_int, [u8p, sz, dbl, u8p, sz, P(sz)]),
+            "hoszp_ref_scalar_sub": (ctypes.c_int, [u8p, sz, dbl, u8p, sz, P(sz)]),
+            "hoszp_ref_std": (ctypes.c_int, [u8p, sz, P(dbl)]),
+            "hoszp_ref_sub": (ctypes.c_int, [u8p, sz, u8p, sz, u8p, sz, P(sz)]),
+            "hoszp_ref_hadamard": (ctypes.c_int, [u8p, sz, u8p, sz, u8p, sz, P(sz)]),
+            "hoszp_ref_covariance": (ctypes.c_int, [u8p, sz, u8p, sz, P(dbl)]),
+            "hoszp_ref_block_means": (ctypes.c_int, [u8p, sz, P(dbl), u64, P(u64)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -189,6 +196,68 @@ def variance(c: np.ndarray) -> float:
     r = ctypes.c_double()
     _check(lib().hoszp_ref_variance(p, c.size, ctypes.byref(r)), "variance")
     return r.value
+
+
+def _shift(fn, c, s):
+    c, p = _u8(c)
+    out = np.zeros(c.size, dtype=np.uint8)
+    nbytes = ctypes.c_size_t(0)
+    _check(fn(p, c.size, float(s), _ptr(out, ctypes.c_uint8), out.size, ctypes.byref(nbytes)),
+           fn.__name__)
+    return out[:nbytes.value].copy()
+
+
+def scalar_add(c: np.ndarray, s: float) -> np.ndarray:
+    return _shift(lib().hoszp_ref_scalar_add, c, s)
+
+
+def scalar_sub(c: np.ndarray, s: float) -> np.ndarray:
+    return _shift(lib().hoszp_ref_scalar_sub, c, s)
+
+
+def std(c: np.ndarray) -> float:
+    c, p = _u8(c)
+    r = ctypes.c_double()
+    _check(lib().hoszp_ref_std(p, c.size, ctypes.byref(r)), "std")
+    return r.value
+
+
+def _bivariate(fn, a, b):
+    a, pa = _u8(a)
+    b, pb = _u8(b)
+    ia = info(a)
+    out, nbytes = _stream_out(ia["n"], ia["block"])
+    _check(fn(pa, a.size, pb, b.size, _ptr(out, ctypes.c_uint8), out.size, ctypes.byref(nbytes)),
+           fn.__name__)
+    return out[:nbytes.value].copy()
+
+
+def sub(a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    return _bivariate(lib().hoszp_ref_sub, a, b)
+
+
+def hadamard(a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    return _bivariate(lib().hoszp_ref_hadamard, a, b)
+
+
+def covariance(a: np.ndarray, b: np.ndarray) -> float:
+    a, pa = _u8(a)
+    b, pb = _u8(b)
+    r = ctypes.c_double()
+    _check(lib().hoszp_ref_covariance(pa, a.size, pb, b.size, ctypes.byref(r)), "covariance")
+    return r.value
+
+
+def block_means(c: np.ndarray):
+    """(per-block means as float64, number of constant blocks)."""
+    c, p = _u8(c)
+    ic = info(c)
+    nb = (ic["n"] + ic["block"] - 1) // ic["block"]
+    m = np.empty(nb, dtype=np.float64)
+    k = ctypes.c_uint64()
+    _check(lib().hoszp_ref_block_means(p, c.size, _ptr(m, ctypes.c_double), nb, ctypes.byref(k)),
+           "block_means")
+    return m, k.value
 
 
 def raw(fn_name: str, *args):

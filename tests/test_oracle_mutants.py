@@ -13,7 +13,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "hoszp_ref.c")
 PINS = ["tests/test_oracle_paper.py", "tests/test_oracle_invariants.py",
-        "tests/test_oracle_exact.py"]
+        "tests/test_oracle_exact.py", "tests/test_oracle_next.py"]
 
 MUTANTS = {
     "eq3_sign": ("double shifted = (double)x[i] + eb;", "double shifted = (double)x[i] - eb;"),
@@ -34,6 +34,21 @@ MUTANTS = {
                              "put_u32(out + g.off_o + 4u * b, o);"),
     "decode_ignores_signs": ("d[k] = get_bit(signs, k) ? -m : m;", "d[k] = m;"),
     "dequantize_scale": ("x[i] = (float)((double)q[i] * two_eb);", "x[i] = (float)((double)q[i] * g.eb);"),
+    "scalar_bin_without_eps": ("double sum = s + eb;", "double sum = s;"),
+    "scalar_sub_adds": ("return shift_outliers(c, c_bytes, s, -1,", "return shift_outliers(c, c_bytes, s, 1,"),
+    "scalar_add_shifts_deltas_too": ("    put_u32(out + g.off_o + 4u * b, (uint32_t)(int32_t)(o + sc.delta));",
+                                     "    put_u32(out + g.off_o + 4u * b, (uint32_t)(int32_t)(o + sc.delta));\n"
+                                     "    out[g.off_p + (b % (g.payload_bytes + 1))] ^= 1u;"),
+    "sub_adds": ("int64_t v = (int64_t)qa[i] - (int64_t)qb[i];", "int64_t v = (int64_t)qa[i] + (int64_t)qb[i];"),
+    "std_without_sqrt": ("*std = sqrt(var);", "*std = var;"),
+    "hadamard_floor_not_half_up": ("i128 rnd = (i128)1 << (sh - 1);", "i128 rnd = 0;"),
+    "hadamard_eps_not_doubled": ("const double two_eb = 2.0 * ga.eb;\n  for", "const double two_eb = ga.eb;\n  for"),
+    "cov_drops_product_of_means": ("i128 m = (i128)ga.n * p - sa * sb;", "i128 m = (i128)ga.n * p;"),
+    "cov_one_scale": ("((2.0 * ga.eb) * (2.0 * gb.eb))", "((2.0 * ga.eb) * (2.0 * ga.eb))"),
+    "block_mean_divides_by_block": ("s->means[b] = ((double)sum / (double)len) * s->two_eb;",
+                                    "s->means[b] = ((double)sum / 32.0) * s->two_eb;"),
+    "constant_block_miscount": ("if (s->widths[b] == 0) s->constant += 1;",
+                                "if (s->widths[b] <= 1) s->constant += 1;"),
 }
 
 
