@@ -153,7 +153,8 @@ int hoszp_decompress_async(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, floa
 /* Negation (Sec. V-A-1, workflow 1): every outlier negated and, in every
  * non-constant block, the sign bits of its valid slots inverted; widths and
  * payload are copied.  out_cap >= the input's total size.  d_out may equal
- * d_c (in place).  The decoded result is exactly the negated field. */
+ * d_c (in place); any other overlap of the two ranges gives ARG.  The decoded
+ * result is exactly the negated field. */
 int hoszp_negate(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, void* d_out, size_t out_cap,
                  size_t* out_bytes, void* stream);
 int hoszp_negate_async(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, void* d_out,
@@ -170,6 +171,34 @@ int hoszp_add(hoszp_ctx* ctx, const void* d_a, size_t a_bytes, const void* d_b, 
 int hoszp_add_async(hoszp_ctx* ctx, const void* d_a, size_t a_bytes, const void* d_b,
                     size_t b_bytes, void* d_out, size_t out_cap, hoszp_result* d_res,
                     void* stream);
+
+/* Element-wise subtraction A - B (Sec. V-C, workflow 2): as hoszp_add with
+ * B's outliers and signed deltas negated; the output is the canonical stream
+ * of the bins q_A - q_B.  Same operand, capacity, range and overlap rules as
+ * hoszp_add. */
+int hoszp_sub(hoszp_ctx* ctx, const void* d_a, size_t a_bytes, const void* d_b, size_t b_bytes,
+              void* d_out, size_t out_cap, size_t* out_bytes, void* stream);
+int hoszp_sub_async(hoszp_ctx* ctx, const void* d_a, size_t a_bytes, const void* d_b,
+                    size_t b_bytes, void* d_out, size_t out_cap, hoszp_result* d_res,
+                    void* stream);
+
+/* Scalar addition / subtraction (Sec. V-A, workflow 1: fully compressed
+ * space).  The scalar's bin q_s = floor((s + eb) * (1 / (2 eb))) (Eq. 3,
+ * evaluated in binary64 like every element) is added to (subtracted from)
+ * every outlier; widths, signs and magnitudes are copied unchanged, so every
+ * decoded bin moves by +-q_s.  s must be finite (ARG); q_s or a shifted bin
+ * outside the bin range gives RANGE.  out_cap >= the input's total size.
+ * d_out may equal d_c (in place: only the outliers are rewritten); any other
+ * overlap gives ARG.  A width pre-pass runs first: blocks whose outlier and
+ * width cannot rule out an out-of-range bin are decoded to check exactly. */
+int hoszp_scalar_add(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, double s, void* d_out,
+                     size_t out_cap, size_t* out_bytes, void* stream);
+int hoszp_scalar_add_async(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, double s,
+                           void* d_out, size_t out_cap, hoszp_result* d_res, void* stream);
+int hoszp_scalar_sub(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, double s, void* d_out,
+                     size_t out_cap, size_t* out_bytes, void* stream);
+int hoszp_scalar_sub_async(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, double s,
+                           void* d_out, size_t out_cap, hoszp_result* d_res, void* stream);
 
 /* Scalar multiplication (Sec. V-A-4, workflow 3): bins decoded, replaced by
  * floor(s * bin + 1/2) computed exactly, then re-encoded.  s must be finite;
@@ -200,6 +229,10 @@ int hoszp_mean_async(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, hoszp_resu
 int hoszp_variance(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, double* var, void* stream);
 int hoszp_variance_async(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, hoszp_result* d_res,
                          void* stream);
+
+/* Standard deviation (Sec. V-B): the square root, taken on the host, of
+ * hoszp_variance's result.  Synchronous only. */
+int hoszp_std(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, double* std, void* stream);
 
 /* ---- decompress-then-compute path (the comparison workflow) ------------ */
 

@@ -111,6 +111,13 @@ _SIGNATURES = {
     "hoszp_mul": (_INT, [_VP, _VP, _SZ, _DBL, _VP, _SZ, ctypes.POINTER(_SZ), _VP]),
     "hoszp_mul_async": (_INT, [_VP, _VP, _SZ, _DBL, _VP, _SZ, _VP, _VP]),
     "hoszp_mul_bins": (_INT, [_DBL, _VP, _VP, _U64]),
+    "hoszp_sub": (_INT, [_VP, _VP, _SZ, _VP, _SZ, _VP, _SZ, ctypes.POINTER(_SZ), _VP]),
+    "hoszp_sub_async": (_INT, [_VP, _VP, _SZ, _VP, _SZ, _VP, _SZ, _VP, _VP]),
+    "hoszp_scalar_add": (_INT, [_VP, _VP, _SZ, _DBL, _VP, _SZ, ctypes.POINTER(_SZ), _VP]),
+    "hoszp_scalar_add_async": (_INT, [_VP, _VP, _SZ, _DBL, _VP, _SZ, _VP, _VP]),
+    "hoszp_scalar_sub": (_INT, [_VP, _VP, _SZ, _DBL, _VP, _SZ, ctypes.POINTER(_SZ), _VP]),
+    "hoszp_scalar_sub_async": (_INT, [_VP, _VP, _SZ, _DBL, _VP, _SZ, _VP, _VP]),
+    "hoszp_std": (_INT, [_VP, _VP, _SZ, ctypes.POINTER(_DBL), _VP]),
     "hoszp_mean": (_INT, [_VP, _VP, _SZ, ctypes.POINTER(_DBL), _VP]),
     "hoszp_mean_async": (_INT, [_VP, _VP, _SZ, _VP, _VP]),
     "hoszp_variance": (_INT, [_VP, _VP, _SZ, ctypes.POINTER(_DBL), _VP]),
@@ -333,6 +340,48 @@ def mul(c, s: float, out=None, stream=None):
     _check(_lib().hoszp_mul(ctx.handle, _ptr(c), _nbytes(c), float(s), _ptr(out), _nbytes(out),
                             ctypes.byref(nb), _stream(stream)), "mul")
     return out[:nb.value]
+
+
+def sub(a, b, out=None, stream=None):
+    """Element-wise subtraction a - b of two streams."""
+    ctx = context(a.device.index)
+    if out is None:
+        h = header_of(a)
+        out = _out_stream(h["n"], h["block"], a.device)
+    nb = _SZ(0)
+    _check(_lib().hoszp_sub(ctx.handle, _ptr(a), _nbytes(a), _ptr(b), _nbytes(b), _ptr(out),
+                            _nbytes(out), ctypes.byref(nb), _stream(stream)), "sub")
+    return out[:nb.value]
+
+
+def _shift(fn, name, c, s, out, stream):
+    import torch
+
+    ctx = context(c.device.index)
+    if out is None:
+        out = torch.empty_like(c)
+    nb = _SZ(0)
+    _check(fn(ctx.handle, _ptr(c), _nbytes(c), float(s), _ptr(out), _nbytes(out),
+              ctypes.byref(nb), _stream(stream)), name)
+    return out[:nb.value]
+
+
+def scalar_add(c, s: float, out=None, stream=None):
+    """Add scalar s to every element (its Eq. 3 bin added to the outliers);
+    out may be c itself."""
+    return _shift(_lib().hoszp_scalar_add, "scalar_add", c, s, out, stream)
+
+
+def scalar_sub(c, s: float, out=None, stream=None):
+    return _shift(_lib().hoszp_scalar_sub, "scalar_sub", c, s, out, stream)
+
+
+def std(c, stream=None) -> float:
+    ctx = context(c.device.index)
+    v = _DBL(0.0)
+    _check(_lib().hoszp_std(ctx.handle, _ptr(c), _nbytes(c), ctypes.byref(v), _stream(stream)),
+           "std")
+    return v.value
 
 
 def mean(c, stream=None) -> float:

@@ -317,7 +317,9 @@ int hoszp_decompress(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, float* d_x
 
 int hoszp_negate_async(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, void* d_out,
                        size_t out_cap, hoszp_result* d_res, void* stream) {
-  if (!stream_args_ok(ctx, d_c, d_res) || !d_out || !aligned(d_out, 16)) return HOSZP_ERR_ARG;
+  if (!stream_args_ok(ctx, d_c, d_res) || !d_out || !aligned(d_out, 16) ||
+      (d_out != d_c && overlap(d_out, out_cap, d_c, c_bytes)))
+    return HOSZP_ERR_ARG;
   DeviceScope scope(ctx->device);
   if (!scope.ok()) return HOSZP_ERR_DEVICE;
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -337,9 +339,9 @@ int hoszp_negate(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, void* d_out, s
   return rc;
 }
 
-int hoszp_add_async(hoszp_ctx* ctx, const void* d_a, size_t a_bytes, const void* d_b,
+static int add_like(hoszp_ctx* ctx, const void* d_a, size_t a_bytes, const void* d_b,
                     size_t b_bytes, void* d_out, size_t out_cap, hoszp_result* d_res,
-                    void* stream) {
+                    void* stream, bool sub) {
   if (!stream_args_ok(ctx, d_a, d_res) || !d_b || !aligned(d_b, 16) || !d_out ||
       !aligned(d_out, 16) || overlap(d_out, out_cap, d_a, a_bytes) ||
       overlap(d_out, out_cap, d_b, b_bytes))
@@ -352,18 +354,80 @@ int hoszp_add_async(hoszp_ctx* ctx, const void* d_a, size_t a_bytes, const void*
   if (rc) return rc;
   return launched(ctx, d_res, st, hz::launch_add(ctx->s, ctx->grids, static_cast<const uint8_t*>(d_a),
                                       a_bytes, static_cast<const uint8_t*>(d_b), b_bytes,
-                                      static_cast<uint8_t*>(d_out), out_cap, epoch, d_res, st));
+                                      static_cast<uint8_t*>(d_out), out_cap, epoch, d_res, st,
+                                      sub));
 }
 
-int hoszp_add(hoszp_ctx* ctx, const void* d_a, size_t a_bytes, const void* d_b, size_t b_bytes,
-              void* d_out, size_t out_cap, size_t* out_bytes, void* stream) {
-  if (!ctx || !out_bytes) return HOSZP_ERR_ARG;
-  int rc = hoszp_add_async(ctx, d_a, a_bytes, d_b, b_bytes, d_out, out_cap, ctx->d_res, stream);
+// Wait for a stream-producing operation enqueued on ctx->d_res.
+static int wait_stream_op(hoszp_ctx* ctx, int rc, size_t* out_bytes, void* stream) {
   if (rc) return rc;
   hoszp_result r;
   rc = hoszp_result_wait(ctx, ctx->d_res, &r, stream);
   if (rc == HOSZP_OK) *out_bytes = size_t(r.out_bytes);
   return rc;
+}
+
+int hoszp_add_async(hoszp_ctx* ctx, const void* d_a, size_t a_bytes, const void* d_b,
+                    size_t b_bytes, void* d_out, size_t out_cap, hoszp_result* d_res,
+                    void* stream) {
+  return add_like(ctx, d_a, a_bytes, d_b, b_bytes, d_out, out_cap, d_res, stream, false);
+}
+
+int hoszp_add(hoszp_ctx* ctx, const void* d_a, size_t a_bytes, const void* d_b, size_t b_bytes,
+              void* d_out, size_t out_cap, size_t* out_bytes, void* stream) {
+  if (!ctx || !out_bytes) return HOSZP_ERR_ARG;
+  return wait_stream_op(ctx, hoszp_add_async(ctx, d_a, a_bytes, d_b, b_bytes, d_out, out_cap,
+                                             ctx->d_res, stream), out_bytes, stream);
+}
+
+int hoszp_sub_async(hoszp_ctx* ctx, const void* d_a, size_t a_bytes, const void* d_b,
+                    size_t b_bytes, void* d_out, size_t out_cap, hoszp_result* d_res,
+                    void* stream) {
+  return add_like(ctx, d_a, a_bytes, d_b, b_bytes, d_out, out_cap, d_res, stream, true);
+}
+
+int hoszp_sub(hoszp_ctx* ctx, const void* d_a, size_t a_bytes, const void* d_b, size_t b_bytes,
+              void* d_out, size_t out_cap, size_t* out_bytes, void* stream) {
+  if (!ctx || !out_bytes) return HOSZP_ERR_ARG;
+  return wait_stream_op(ctx, hoszp_sub_async(ctx, d_a, a_bytes, d_b, b_bytes, d_out, out_cap,
+                                             ctx->d_res, stream), out_bytes, stream);
+}
+
+static int shift_async(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, double s, int sign,
+                       void* d_out, size_t out_cap, hoszp_result* d_res, void* stream) {
+  if (!stream_args_ok(ctx, d_c, d_res) || !d_out || !aligned(d_out, 16) || !isfinite(s) ||
+      (d_out != d_c && overlap(d_out, out_cap, d_c, c_bytes)))
+    return HOSZP_ERR_ARG;
+  DeviceScope scope(ctx->device);
+  if (!scope.ok()) return HOSZP_ERR_DEVICE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  return launched(ctx, d_res, st, hz::launch_shift(ctx->s, ctx->grids,
+                                        static_cast<const uint8_t*>(d_c), c_bytes, s, sign,
+                                        static_cast<uint8_t*>(d_out), out_cap, d_res, st));
+}
+
+int hoszp_scalar_add_async(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, double s,
+                           void* d_out, size_t out_cap, hoszp_result* d_res, void* stream) {
+  return shift_async(ctx, d_c, c_bytes, s, 1, d_out, out_cap, d_res, stream);
+}
+
+int hoszp_scalar_sub_async(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, double s,
+                           void* d_out, size_t out_cap, hoszp_result* d_res, void* stream) {
+  return shift_async(ctx, d_c, c_bytes, s, -1, d_out, out_cap, d_res, stream);
+}
+
+int hoszp_scalar_add(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, double s, void* d_out,
+                     size_t out_cap, size_t* out_bytes, void* stream) {
+  if (!ctx || !out_bytes) return HOSZP_ERR_ARG;
+  return wait_stream_op(ctx, shift_async(ctx, d_c, c_bytes, s, 1, d_out, out_cap, ctx->d_res,
+                                         stream), out_bytes, stream);
+}
+
+int hoszp_scalar_sub(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, double s, void* d_out,
+                     size_t out_cap, size_t* out_bytes, void* stream) {
+  if (!ctx || !out_bytes) return HOSZP_ERR_ARG;
+  return wait_stream_op(ctx, shift_async(ctx, d_c, c_bytes, s, -1, d_out, out_cap, ctx->d_res,
+                                         stream), out_bytes, stream);
 }
 
 int hoszp_mul_async(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, double s, void* d_out,
@@ -446,6 +510,14 @@ int hoszp_variance(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, double* var,
   hoszp_result r;
   rc = hoszp_result_wait(ctx, ctx->d_res, &r, stream);
   if (rc == HOSZP_OK) *var = r.value;
+  return rc;
+}
+
+int hoszp_std(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, double* std, void* stream) {
+  if (!ctx || !std) return HOSZP_ERR_ARG;
+  double var = 0.0;
+  const int rc = hoszp_variance(ctx, d_c, c_bytes, &var, stream);
+  if (rc == HOSZP_OK) *std = sqrt(var);  // correctly rounded (IEEE sqrt on the host)
   return rc;
 }
 

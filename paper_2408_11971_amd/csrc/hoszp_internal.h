@@ -186,9 +186,14 @@ hipError_t launch_reduce(const Scratch& s, const Grids& gr, const uint8_t* c, ui
                          bool variance, uint32_t epoch, hoszp_result* res, hipStream_t st);
 hipError_t launch_negate(const Scratch& s, const Grids& gr, const uint8_t* c, uint64_t c_bytes,
                          uint8_t* out, uint64_t out_cap, hoszp_result* res, hipStream_t st);
+// Scalar addition (sign +1) or subtraction (sign -1) on the outliers.
+hipError_t launch_shift(const Scratch& s, const Grids& gr, const uint8_t* c, uint64_t c_bytes,
+                        double scalar, int sign, uint8_t* out, uint64_t out_cap,
+                        hoszp_result* res, hipStream_t st);
+// Element-wise addition, or subtraction a - b when `sub`.
 hipError_t launch_add(const Scratch& s, const Grids& gr, const uint8_t* a, uint64_t a_bytes,
                       const uint8_t* b, uint64_t b_bytes, uint8_t* out, uint64_t out_cap,
-                      uint32_t epoch, hoszp_result* res, hipStream_t st);
+                      uint32_t epoch, hoszp_result* res, hipStream_t st, bool sub = false);
 hipError_t launch_mul(const Scratch& s, const Grids& gr, const uint8_t* c, uint64_t c_bytes,
                       MulScalar k, uint8_t* out, uint64_t out_cap, uint32_t epoch,
                       hoszp_result* res, hipStream_t st);

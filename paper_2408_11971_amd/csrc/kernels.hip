@@ -1477,22 +1477,85 @@ struct NegateParams {
   uint64_t out_cap;
   Scratch s;
   hoszp_result* res;
+  double scalar;  // kShift: the scalar s
+  int32_t sign;   // kShift: +1 adds the scalar's bin, -1 subtracts it
+  int32_t pad;
 };
 
-// Negation streams the stream in 16-byte chunks: widths, header, padding and
-// payload are copied (widths summed and range-checked on the way), outliers
-// negated, and the sign bits of valid slots of non-constant blocks flipped.
+enum { kNegate = 0, kShift = 1 };
+
+// Smallest and largest prefix sum of block `blk`'s deltas (0 included: slot
+// 0's bin is the outlier), read one field at a time from the stream's
+// payload, found through the width pre-pass index.  The slow path of the
+// scalar-shift range check: taken only by blocks whose outlier and width
+// allow a bin to leave the range, so one lane decoding its block is enough.
+// False when the widths place the block outside the payload (a malformed
+// stream, which the width pre-pass also reports): nothing is read then.
+__device__ __noinline__ bool block_prefix_range(const uint8_t* c, const Layout& g,
+                                                const TileIndex& ix, uint64_t blk, uint32_t w,
+                                                uint32_t len, int64_t& lo, int64_t& hi) {
+  const uint64_t seg0 = blk << g.spb_log2;
+  const uint64_t wt = seg0 / kWaveSegs, chunk = wt / kChunkTiles;
+  uint64_t off = ix.chunk_off[chunk];
+  for (uint64_t t = chunk * kChunkTiles; t < wt; ++t) off += ix.tile_words[t];
+  for (uint64_t b = (wt * kWaveSegs) >> g.spb_log2; b < blk; ++b)
+    off += min(uint64_t(c[g.off_w + b]), uint64_t(32)) * g.spb;
+  lo = 0;
+  hi = 0;
+  if (off + uint64_t(w) * g.spb > g.payload_bytes / 4) return false;
+  const uint32_t* P = reinterpret_cast<const uint32_t*>(c + g.off_p) + off;
+  const uint8_t* S = c + g.off_s + blk * (g.L / 8);
+  int64_t e = 0;
+  for (uint32_t k = 1; k < len; ++k) {
+    const uint32_t bit = k * w, i = bit >> 5, sh = bit & 31u;
+    const uint64_t win = (uint64_t(bswap32(P[i])) << 32) | (sh + w > 32 ? bswap32(P[i + 1]) : 0u);
+    const uint32_t m = uint32_t((win << sh) >> (64u - w));
+    e += ((S[k >> 3] >> (7u - (k & 7u))) & 1u) ? -int64_t(m) : int64_t(m);
+    lo = e < lo ? e : lo;
+    hi = e > hi ? e : hi;
+  }
+  return true;
+}
+
+// The scalar's bin by Eq. 3, evaluated as for every element (two rounded
+// binary64 operations and the floor); ST_RANGE outside the bin range.
+__device__ __forceinline__ int64_t scalar_bin(double s, double eb, uint32_t& bad) {
+  const double inv = 1.0 / (2.0 * eb);
+  const double f = floor((s + eb) * inv);
+  if (!(f >= -kBinMaxD && f <= kBinMaxD)) {
+    bad |= ST_RANGE;
+    return 0;
+  }
+  return int64_t(f);
+}
+
+// Workflow 1 of Sec. V-A on the outliers, streaming the stream in 16-byte
+// chunks: widths (summed and range-checked on the way), header, padding and
+// payload are copied, and
+//   kNegate: outliers negated, sign bits of valid slots of non-constant
+//            blocks flipped (Sec. V-A negation);
+//   kShift:  the scalar's bin added to (sign -1: subtracted from) every
+//            outlier, signs copied (Sec. V-A scalar addition/subtraction);
+//            every shifted bin must stay in range: blocks whose outlier and
+//            width leave no doubt pass at once, the others are decoded
+//            (block_prefix_range, via the width pre-pass index in idx[0]).
+// In place (out == c) kShift touches only the width and outlier sections.
+template <int MODE>
 __global__ void __launch_bounds__(kThreads) k_negate(NegateParams p) {
   __shared__ uint32_t s_flag;
   const int tid = threadIdx.x;
   Layout g;
   uint32_t err = read_header(p.c, p.c_bytes, g);
   if (!err && p.out_cap < g.total_bytes) err = ST_CAPACITY;
+  uint32_t bad = 0;
+  int64_t delta = 0;
+  if (MODE == kShift && !err) delta = p.sign * scalar_bin(p.scalar, g.eb, err);
   if (tid == 0 && blockIdx.x == 0) latch(p.s, err);
+  const bool in_place = MODE == kShift && p.out == p.c;
   const uint64_t nfull = err ? 0 : g.total_bytes / 16;  // whole 16-byte chunks
+  const uint64_t kbeg = in_place ? g.off_w / 16 : 0, kend = in_place ? g.off_s / 16 : nfull;
   const uint64_t stride = uint64_t(gridDim.x) * kThreads;
   uint64_t wsum = 0;
-  uint32_t bad = 0;
   const uint4* src = reinterpret_cast<const uint4*>(p.c);
   uint4* dst = reinterpret_cast<uint4*>(p.out);
   const uint32_t* W32 = reinterpret_cast<const uint32_t*>(p.c + g.off_w);  // 16-byte aligned
@@ -1501,23 +1564,30 @@ __global__ void __launch_bounds__(kThreads) k_negate(NegateParams p) {
   // written (no lane condition on the loads: past the end a thread reloads the
   // last chunk and drops it), so the loads of a round are in flight together.
   constexpr int kNegUnroll = 4;
-  for (uint64_t k0 = uint64_t(blockIdx.x) * kThreads + tid; k0 < nfull; k0 += kNegUnroll * stride) {
+  for (uint64_t k0 = kbeg + uint64_t(blockIdx.x) * kThreads + tid; k0 < kend;
+       k0 += kNegUnroll * stride) {
     uint4 v[kNegUnroll];
-    uint32_t wq[kNegUnroll];  // sign chunks: the aligned width word holding their blocks
+    uint32_t wq[kNegUnroll];  // the aligned width word holding the chunk's blocks
 #pragma unroll
     for (int u = 0; u < kNegUnroll; ++u) {
-      const uint64_t k = min(k0 + uint64_t(u) * stride, nfull - 1);
+      const uint64_t k = min(k0 + uint64_t(u) * stride, kend - 1);
       v[u] = src[k];
       const uint64_t o = 16 * k;
-      // a sign chunk's four segments are consecutive and start at a multiple
-      // of 4, so their blocks lie in one aligned 4-byte word of the widths
-      const uint64_t sg = (o >= g.off_s && o < s_end) ? (o - g.off_s) / 4 : 0;
-      wq[u] = W32[(sg >> g.spb_log2) >> 2];
+      if (MODE == kNegate) {
+        // a sign chunk's four segments are consecutive and start at a
+        // multiple of 4, so their blocks lie in one aligned word of widths
+        const uint64_t sg = (o >= g.off_s && o < s_end) ? (o - g.off_s) / 4 : 0;
+        wq[u] = W32[(sg >> g.spb_log2) >> 2];
+      } else {
+        // an outlier chunk's four blocks start at a multiple of 4
+        const uint64_t b0 = (o >= g.off_o && o < o_end) ? (o - g.off_o) / 4 : 0;
+        wq[u] = W32[b0 >> 2];
+      }
     }
 #pragma unroll
     for (int u = 0; u < kNegUnroll; ++u) {
       const uint64_t k = k0 + uint64_t(u) * stride;
-      if (k >= nfull) continue;
+      if (k >= kend) continue;
       const uint64_t o = 16 * k;
       uint32_t wd[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
       if (o >= g.off_p || o + 16 <= g.off_w) {
@@ -1532,11 +1602,31 @@ __global__ void __launch_bounds__(kThreads) k_negate(NegateParams p) {
           if ((x | ((x & 0x7f7f7f7fu) + 0x5f5f5f5fu)) & 0x80808080u) bad |= ST_FORMAT;
           wsum += __builtin_amdgcn_sad_u8(x, 0u, 0u);
         }
-      } else if (o < g.off_s) {  // outliers: O -> -O
+      } else if (o < g.off_s) {  // outliers
+        if (MODE == kNegate) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-          if (o + 4 * q < o_end) wd[q] = 0u - wd[q];
-      } else {  // signs
+          for (int q = 0; q < 4; ++q)
+            if (o + 4 * q < o_end) wd[q] = 0u - wd[q];
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            if (o + 4 * q >= o_end) continue;
+            const uint64_t blk = (o - g.off_o) / 4 + q;
+            const int64_t ov = int32_t(wd[q]);
+            const uint32_t w = min((wq[u] >> (8 * q)) & 0xffu, 32u);
+            uint64_t blen = g.L;
+            if (blk == g.nb - 1) (void)seg_count(g, blk, 0, blen);
+            if (!bins_surely_in_range(ov, blen, w) || !bins_surely_in_range(ov + delta, blen, w)) {
+              int64_t lo = 0, hi = 0;
+              if (w > 0 && !block_prefix_range(p.c, g, p.s.idx[0], blk, w, uint32_t(blen), lo, hi))
+                bad |= ST_FORMAT;
+              if (ov + lo < -kBinMax || ov + hi > kBinMax) bad |= ST_FORMAT;
+              else if (ov + delta + lo < -kBinMax || ov + delta + hi > kBinMax) bad |= ST_RANGE;
+            }
+            wd[q] = uint32_t(int32_t(ov + delta));
+          }
+        }
+      } else if (MODE == kNegate) {  // signs
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const uint64_t b0 = o + 4 * q;
@@ -1558,7 +1648,7 @@ __global__ void __launch_bounds__(kThreads) k_negate(NegateParams p) {
     }
   }
   // the last partial chunk (payload words only): one thread
-  if (!err && blockIdx.x == 0 && tid == 0)
+  if (!err && !in_place && blockIdx.x == 0 && tid == 0)
     for (uint64_t b = 16 * nfull; b < g.total_bytes; b += 4)
       *reinterpret_cast<uint32_t*>(p.out + b) = *reinterpret_cast<const uint32_t*>(p.c + b);
   latch(p.s, bad);
@@ -1583,12 +1673,13 @@ struct AddParams {
   hoszp_result* res;
 };
 
-// Element-wise addition, one tile of NT segments per workgroup.  The two
-// operands' payloads share one tile's LDS buffer: both at once when their
-// words fit (B right after A), else one after the other (A's magnitudes held
-// in registers while B's payload replaces A's), so the workgroup never needs
-// two tiles of LDS.
-template <int NT>
+// Element-wise addition (Sec. V-C), one tile of NT segments per workgroup;
+// SUB: element-wise subtraction A - B, the same with B's outlier negated and
+// the signs of B's deltas inverted.  The two operands' payloads share one
+// tile's LDS buffer: both at once when their words fit (B right after A),
+// else one after the other (A's magnitudes held in registers while B's
+// payload replaces A's), so the workgroup never needs two tiles of LDS.
+template <int NT, bool SUB>
 __global__ void __launch_bounds__(NT) k_add(AddParams p) {
   __shared__ uint32_t s_pay[NT * 32 + 2];
   __shared__ uint32_t s_tmp[NT / 64];
@@ -1635,7 +1726,8 @@ __global__ void __launch_bounds__(NT) k_add(AddParams p) {
     const int32_t oa32 = Oa[mblk], ob32 = Ob[mblk];
     const uint32_t wa8 = p.a[g.off_w + mblk], wb8 = p.b[gb.off_w + mblk];
     const uint32_t swa8 = Sa[mseg], swb8 = Sb[mseg];
-    const int64_t oa = active ? oa32 : 0, ob = active ? ob32 : 0;
+    const int64_t oa = active ? oa32 : 0;
+    const int64_t ob = active ? (SUB ? -int64_t(ob32) : int64_t(ob32)) : 0;
     uint32_t bad = 0;
     // widths of both operands, scanned together in the 16-bit halves of one
     // word (a tile holds at most 32 NT payload words per operand)
@@ -1665,7 +1757,7 @@ __global__ void __launch_bounds__(NT) k_add(AddParams p) {
     else
       stage_words<NT, false>(s_pay, Pa + base_a, fits_a ? tw_a : 0u, nullptr, 0u);
     const uint32_t swa = (cnt > 0 && wa) ? bswap32(swa8) : 0u;
-    const uint32_t swb = (cnt > 0 && wb) ? bswap32(swb8) : 0u;
+    const uint32_t swb = (cnt > 0 && wb) ? (SUB ? ~bswap32(swb8) : bswap32(swb8)) : 0u;
     __syncthreads();
     // operand A's magnitudes are kept in registers
     uint32_t ma[32];
@@ -2130,19 +2222,32 @@ hipError_t launch_reduce(const Scratch& s, const Grids& gr, const uint8_t* c, ui
 
 hipError_t launch_negate(const Scratch& s, const Grids& gr, const uint8_t* c, uint64_t c_bytes,
                          uint8_t* out, uint64_t out_cap, hoszp_result* res, hipStream_t st) {
-  NegateParams p{c, c_bytes, out, out_cap, s, res};
-  hipLaunchKernelGGL(k_negate, dim3(gr.negate), dim3(kThreads), 0, st, p);
+  NegateParams p{c, c_bytes, out, out_cap, s, res, 0.0, 0, 0};
+  hipLaunchKernelGGL(k_negate<kNegate>, dim3(gr.negate), dim3(kThreads), 0, st, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_shift(const Scratch& s, const Grids& gr, const uint8_t* c, uint64_t c_bytes,
+                        double scalar, int sign, uint8_t* out, uint64_t out_cap,
+                        hoszp_result* res, hipStream_t st) {
+  hipError_t e = launch_widths(s, gr, 0, c, c_bytes, st);
+  if (e != hipSuccess) return e;
+  NegateParams p{c, c_bytes, out, out_cap, s, res, scalar, sign, 0};
+  hipLaunchKernelGGL(k_negate<kShift>, dim3(gr.negate), dim3(kThreads), 0, st, p);
   return hipGetLastError();
 }
 
 hipError_t launch_add(const Scratch& s, const Grids& gr, const uint8_t* a, uint64_t a_bytes,
                       const uint8_t* b, uint64_t b_bytes, uint8_t* out, uint64_t out_cap,
-                      uint32_t epoch, hoszp_result* res, hipStream_t st) {
+                      uint32_t epoch, hoszp_result* res, hipStream_t st, bool sub) {
   hipError_t e = launch_widths(s, gr, 0, a, a_bytes, st);
   if (e == hipSuccess) e = launch_widths(s, gr, 1, b, b_bytes, st);
   if (e != hipSuccess) return e;
   AddParams p{a, a_bytes, b, b_bytes, out, out_cap, s, epoch, res};
-  hipLaunchKernelGGL(k_add<kAddThreads>, dim3(gr.add), dim3(kAddThreads), 0, st, p);
+  if (sub)
+    hipLaunchKernelGGL((k_add<kAddThreads, true>), dim3(gr.add), dim3(kAddThreads), 0, st, p);
+  else
+    hipLaunchKernelGGL((k_add<kAddThreads, false>), dim3(gr.add), dim3(kAddThreads), 0, st, p);
   return hipGetLastError();
 }
 
@@ -2197,7 +2302,7 @@ hipError_t query_grids(Grids& gr, int num_cus) {
   int r = 0;
   if (e == hipSuccess)
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&r, k_decode<kMean>, kReduceThreads, 0);
-  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_add<kAddThreads>, kAddThreads, 0);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_add<kAddThreads, false>, kAddThreads, 0);
   if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&m, k_mul<kMulThreads>, kMulThreads, 0);
   if (e != hipSuccess) return e;
   auto clampg = [&](int occ) { return num_cus * (occ < 1 ? 1 : occ); };

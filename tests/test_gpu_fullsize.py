@@ -119,6 +119,10 @@ def test_fullsize_homomorphic_ops(fields, rel):
                  lambda i, j: ref.mul(ref.compress(a[i:j], eb, L), 3.14))
     check_slices(hz.negate(cb).cpu().numpy(), n, slices,
                  lambda i, j: ref.negate(ref.compress(b[i:j], eb, L)))
+    check_slices(hz.sub(ca, cb).cpu().numpy(), n, slices,
+                 lambda i, j: ref.sub(ref.compress(a[i:j], eb, L), ref.compress(b[i:j], eb, L)))
+    check_slices(hz.scalar_add(cb, -0.37).cpu().numpy(), n, slices,
+                 lambda i, j: ref.scalar_add(ref.compress(b[i:j], eb, L), -0.37))
 
 
 # ------------------------------------------- 1800 x 3600 climate-like steps
@@ -150,9 +154,14 @@ def test_fullsize_climate_steps(climate, block):
         assert np.array_equal(hz.negate(c).cpu().numpy(), ref.negate(xc)), f"negate step {t}"
         assert np.array_equal(hz.mul(c, float(s[t])).cpu().numpy(), ref.mul(xc, float(s[t]))), \
             f"mul step {t}"
+        assert np.array_equal(hz.scalar_add(c, float(s[t])).cpu().numpy(),
+                              ref.scalar_add(xc, float(s[t]))), f"scalar add step {t}"
+        assert abs(hz.std(c) - ref.std(xc)) <= 1e-12 * ref.std(xc)
         if prev is not None:
             # pairwise step add: both operands at this step's eb (add needs equal eb)
             pc = ref.compress(prev, eb, block)
             got = hz.add(hz.compress(torch.from_numpy(prev).to(dev), eb, block), c)
             assert np.array_equal(got.cpu().numpy(), ref.add(pc, xc)), f"add steps {t-1}+{t}"
+            got = hz.sub(c, hz.compress(torch.from_numpy(prev).to(dev), eb, block))
+            assert np.array_equal(got.cpu().numpy(), ref.sub(xc, pc)), f"sub steps {t}-{t-1}"
         prev = x
