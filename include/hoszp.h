@@ -80,14 +80,17 @@ extern "C" {
  * device memory (64 bytes, 8-byte aligned).
  *   status     bit (1 << code) set for every error the kernels detected;
  *              0 = success.  hoszp_status_code() picks the reported code.
- *   out_bytes  size of the produced stream (compress, negate, add, mul).
- *   value      mean or variance (mean, variance). */
+ *   out_bytes  size of the produced stream (compress, negate, add, mul, ...).
+ *   value      mean, variance or covariance (reductions; block means: the
+ *              field's mean).
+ *   count      block means: the number of constant (width 0) blocks. */
 typedef struct hoszp_result {
   uint32_t status;
   uint32_t reserved0;
   uint64_t out_bytes;
   double value;
-  uint64_t reserved[5];
+  uint64_t count;
+  uint64_t reserved[4];
 } hoszp_result;
 
 /* Host-side view of a stream header. */
@@ -229,6 +232,42 @@ int hoszp_mean_async(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, hoszp_resu
 int hoszp_variance(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, double* var, void* stream);
 int hoszp_variance_async(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, hoszp_result* d_res,
                          void* stream);
+
+/* Hadamard product (Sec. V-C, workflow 3): both operands' bins decoded,
+ * multiplied element by element and re-quantized at the same eb with half-up
+ * rounding, exactly: q = floor(2 eb q_A q_B + 1/2) (the decoded product
+ * (2 eb)^2 q_A q_B over the bin width 2 eb, rounded as scalar
+ * multiplication rounds), then re-encoded canonically.  Operands as
+ * hoszp_add (equal n, block size and eb bits, else MISMATCH); a product bin
+ * outside the bin range gives RANGE; d_out must not overlap the inputs. */
+int hoszp_hadamard(hoszp_ctx* ctx, const void* d_a, size_t a_bytes, const void* d_b,
+                   size_t b_bytes, void* d_out, size_t out_cap, size_t* out_bytes, void* stream);
+int hoszp_hadamard_async(hoszp_ctx* ctx, const void* d_a, size_t a_bytes, const void* d_b,
+                         size_t b_bytes, void* d_out, size_t out_cap, hoszp_result* d_res,
+                         void* stream);
+
+/* Population covariance of two decoded fields (Sec. V-D):
+ * ((double)(n P - S_A S_B) / n / n) * (2 eb_A)(2 eb_B) with S = sum of bins
+ * and P = sum q_A q_B held exactly (128-bit).  The operands need equal n and
+ * block size (MISMATCH otherwise); their error bounds may differ.  The async
+ * variant puts the value in d_res->value. */
+int hoszp_covariance(hoszp_ctx* ctx, const void* d_a, size_t a_bytes, const void* d_b,
+                     size_t b_bytes, double* cov, void* stream);
+int hoszp_covariance_async(hoszp_ctx* ctx, const void* d_a, size_t a_bytes, const void* d_b,
+                           size_t b_bytes, hoszp_result* d_res, void* stream);
+
+/* Block-wise means (Sec. V-B: the mean kernel applied per block) and the
+ * constant-block count (the statistic of Table VI): d_means[b] =
+ * ((double)S_b / len_b) * 2 eb for every block b, S_b the exact sum of the
+ * block's bins and len_b its length (the last block may be short);
+ * *constant_blocks = blocks of width 0 (all bins equal).  d_means is a
+ * caller-owned device array of means_cap >= nb doubles (8-byte aligned;
+ * CAPACITY otherwise).  The async variant puts the count in d_res->count and
+ * the field's mean in d_res->value. */
+int hoszp_block_means(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, double* d_means,
+                      uint64_t means_cap, uint64_t* constant_blocks, void* stream);
+int hoszp_block_means_async(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, double* d_means,
+                            uint64_t means_cap, hoszp_result* d_res, void* stream);
 
 /* Standard deviation (Sec. V-B): the square root, taken on the host, of
  * hoszp_variance's result.  Synchronous only. */

@@ -35,7 +35,7 @@ class HoszpError(RuntimeError):
 class Result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_uint32), ("reserved0", ctypes.c_uint32),
                 ("out_bytes", ctypes.c_uint64), ("value", ctypes.c_double),
-                ("reserved", ctypes.c_uint64 * 5)]
+                ("count", ctypes.c_uint64), ("reserved", ctypes.c_uint64 * 4)]
 
 
 class Info(ctypes.Structure):
@@ -118,6 +118,12 @@ _SIGNATURES = {
     "hoszp_scalar_sub": (_INT, [_VP, _VP, _SZ, _DBL, _VP, _SZ, ctypes.POINTER(_SZ), _VP]),
     "hoszp_scalar_sub_async": (_INT, [_VP, _VP, _SZ, _DBL, _VP, _SZ, _VP, _VP]),
     "hoszp_std": (_INT, [_VP, _VP, _SZ, ctypes.POINTER(_DBL), _VP]),
+    "hoszp_hadamard": (_INT, [_VP, _VP, _SZ, _VP, _SZ, _VP, _SZ, ctypes.POINTER(_SZ), _VP]),
+    "hoszp_hadamard_async": (_INT, [_VP, _VP, _SZ, _VP, _SZ, _VP, _SZ, _VP, _VP]),
+    "hoszp_covariance": (_INT, [_VP, _VP, _SZ, _VP, _SZ, ctypes.POINTER(_DBL), _VP]),
+    "hoszp_covariance_async": (_INT, [_VP, _VP, _SZ, _VP, _SZ, _VP, _VP]),
+    "hoszp_block_means": (_INT, [_VP, _VP, _SZ, _VP, _U64, ctypes.POINTER(_U64), _VP]),
+    "hoszp_block_means_async": (_INT, [_VP, _VP, _SZ, _VP, _U64, _VP, _VP]),
     "hoszp_mean": (_INT, [_VP, _VP, _SZ, ctypes.POINTER(_DBL), _VP]),
     "hoszp_mean_async": (_INT, [_VP, _VP, _SZ, _VP, _VP]),
     "hoszp_variance": (_INT, [_VP, _VP, _SZ, ctypes.POINTER(_DBL), _VP]),
@@ -264,7 +270,8 @@ def read_result(res, ctx=None, stream=None) -> dict:
     ctx = ctx or context(res.device.index)
     r = Result()
     code = _lib().hoszp_result_wait(ctx.handle, _ptr(res), ctypes.byref(r), _stream(stream))
-    return {"code": code, "status": r.status, "out_bytes": r.out_bytes, "value": r.value}
+    return {"code": code, "status": r.status, "out_bytes": r.out_bytes, "value": r.value,
+            "count": r.count}
 
 
 def header_of(c) -> dict:
@@ -374,6 +381,40 @@ def scalar_add(c, s: float, out=None, stream=None):
 
 def scalar_sub(c, s: float, out=None, stream=None):
     return _shift(_lib().hoszp_scalar_sub, "scalar_sub", c, s, out, stream)
+
+
+def hadamard(a, b, out=None, stream=None):
+    """Element-wise product of two streams (same n, block size and eb)."""
+    ctx = context(a.device.index)
+    if out is None:
+        h = header_of(a)
+        out = _out_stream(h["n"], h["block"], a.device)
+    nb = _SZ(0)
+    _check(_lib().hoszp_hadamard(ctx.handle, _ptr(a), _nbytes(a), _ptr(b), _nbytes(b), _ptr(out),
+                                 _nbytes(out), ctypes.byref(nb), _stream(stream)), "hadamard")
+    return out[:nb.value]
+
+
+def covariance(a, b, stream=None) -> float:
+    ctx = context(a.device.index)
+    v = _DBL(0.0)
+    _check(_lib().hoszp_covariance(ctx.handle, _ptr(a), _nbytes(a), _ptr(b), _nbytes(b),
+                                   ctypes.byref(v), _stream(stream)), "covariance")
+    return v.value
+
+
+def block_means(c, out=None, stream=None):
+    """(float64 tensor of the per-block means, number of constant blocks)."""
+    import torch
+
+    ctx = context(c.device.index)
+    h = header_of(c)
+    if out is None:
+        out = torch.empty(h["nb"], dtype=torch.float64, device=c.device)
+    k = _U64(0)
+    _check(_lib().hoszp_block_means(ctx.handle, _ptr(c), _nbytes(c), _ptr(out), out.numel(),
+                                    ctypes.byref(k), _stream(stream)), "block_means")
+    return out[:h["nb"]], k.value
 
 
 def std(c, stream=None) -> float:

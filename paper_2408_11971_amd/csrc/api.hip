@@ -513,6 +513,77 @@ int hoszp_variance(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, double* var,
   return rc;
 }
 
+int hoszp_hadamard_async(hoszp_ctx* ctx, const void* d_a, size_t a_bytes, const void* d_b,
+                         size_t b_bytes, void* d_out, size_t out_cap, hoszp_result* d_res,
+                         void* stream) {
+  if (!stream_args_ok(ctx, d_a, d_res) || !d_b || !aligned(d_b, 16) || !d_out ||
+      !aligned(d_out, 16) || overlap(d_out, out_cap, d_a, a_bytes) ||
+      overlap(d_out, out_cap, d_b, b_bytes))
+    return HOSZP_ERR_ARG;
+  DeviceScope scope(ctx->device);
+  if (!scope.ok()) return HOSZP_ERR_DEVICE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  uint32_t epoch;
+  int rc = next_epoch(ctx, st, &epoch);
+  if (rc) return rc;
+  return launched(ctx, d_res, st, hz::launch_bivar(ctx->s, ctx->grids, false,
+                                        static_cast<const uint8_t*>(d_a), a_bytes,
+                                        static_cast<const uint8_t*>(d_b), b_bytes,
+                                        static_cast<uint8_t*>(d_out), out_cap, epoch, d_res, st));
+}
+
+int hoszp_hadamard(hoszp_ctx* ctx, const void* d_a, size_t a_bytes, const void* d_b,
+                   size_t b_bytes, void* d_out, size_t out_cap, size_t* out_bytes, void* stream) {
+  if (!ctx || !out_bytes) return HOSZP_ERR_ARG;
+  return wait_stream_op(ctx, hoszp_hadamard_async(ctx, d_a, a_bytes, d_b, b_bytes, d_out, out_cap,
+                                                  ctx->d_res, stream), out_bytes, stream);
+}
+
+int hoszp_covariance_async(hoszp_ctx* ctx, const void* d_a, size_t a_bytes, const void* d_b,
+                           size_t b_bytes, hoszp_result* d_res, void* stream) {
+  if (!stream_args_ok(ctx, d_a, d_res) || !d_b || !aligned(d_b, 16)) return HOSZP_ERR_ARG;
+  DeviceScope scope(ctx->device);
+  if (!scope.ok()) return HOSZP_ERR_DEVICE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  return launched(ctx, d_res, st, hz::launch_bivar(ctx->s, ctx->grids, true,
+                                        static_cast<const uint8_t*>(d_a), a_bytes,
+                                        static_cast<const uint8_t*>(d_b), b_bytes, nullptr, 0,
+                                        0, d_res, st));
+}
+
+int hoszp_covariance(hoszp_ctx* ctx, const void* d_a, size_t a_bytes, const void* d_b,
+                     size_t b_bytes, double* cov, void* stream) {
+  if (!ctx || !cov) return HOSZP_ERR_ARG;
+  int rc = hoszp_covariance_async(ctx, d_a, a_bytes, d_b, b_bytes, ctx->d_res, stream);
+  if (rc) return rc;
+  hoszp_result r;
+  rc = hoszp_result_wait(ctx, ctx->d_res, &r, stream);
+  if (rc == HOSZP_OK) *cov = r.value;
+  return rc;
+}
+
+int hoszp_block_means_async(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, double* d_means,
+                            uint64_t means_cap, hoszp_result* d_res, void* stream) {
+  if (!stream_args_ok(ctx, d_c, d_res) || !d_means || !aligned(d_means, 8)) return HOSZP_ERR_ARG;
+  DeviceScope scope(ctx->device);
+  if (!scope.ok()) return HOSZP_ERR_DEVICE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  return launched(ctx, d_res, st, hz::launch_block_means(ctx->s, ctx->grids,
+                                              static_cast<const uint8_t*>(d_c), c_bytes,
+                                              d_means, means_cap, d_res, st));
+}
+
+int hoszp_block_means(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, double* d_means,
+                      uint64_t means_cap, uint64_t* constant_blocks, void* stream) {
+  if (!ctx || !constant_blocks) return HOSZP_ERR_ARG;
+  int rc = hoszp_block_means_async(ctx, d_c, c_bytes, d_means, means_cap, ctx->d_res, stream);
+  if (rc) return rc;
+  hoszp_result r;
+  rc = hoszp_result_wait(ctx, ctx->d_res, &r, stream);
+  if (rc == HOSZP_OK) *constant_blocks = r.count;
+  return rc;
+}
+
 int hoszp_std(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, double* std, void* stream) {
   if (!ctx || !std) return HOSZP_ERR_ARG;
   double var = 0.0;

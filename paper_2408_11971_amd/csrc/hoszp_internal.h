@@ -169,7 +169,7 @@ inline __host__ __device__ uint64_t batch_tiles(const Layout& g) {
 
 // Occupancy-derived persistent grid sizes, filled at context creation.
 struct Grids {
-  int compress, decode, reduce, add, mul, negate, widths, f32;
+  int compress, decode, reduce, add, mul, negate, widths, f32, bivar;
 };
 
 // ---- launchers (kernels.hip) ----------------------------------------------
@@ -186,6 +186,9 @@ hipError_t launch_reduce(const Scratch& s, const Grids& gr, const uint8_t* c, ui
                          bool variance, uint32_t epoch, hoszp_result* res, hipStream_t st);
 hipError_t launch_negate(const Scratch& s, const Grids& gr, const uint8_t* c, uint64_t c_bytes,
                          uint8_t* out, uint64_t out_cap, hoszp_result* res, hipStream_t st);
+hipError_t launch_block_means(const Scratch& s, const Grids& gr, const uint8_t* c,
+                              uint64_t c_bytes, double* means, uint64_t means_cap,
+                              hoszp_result* res, hipStream_t st);
 // Scalar addition (sign +1) or subtraction (sign -1) on the outliers.
 hipError_t launch_shift(const Scratch& s, const Grids& gr, const uint8_t* c, uint64_t c_bytes,
                         double scalar, int sign, uint8_t* out, uint64_t out_cap,
@@ -197,6 +200,10 @@ hipError_t launch_add(const Scratch& s, const Grids& gr, const uint8_t* a, uint6
 hipError_t launch_mul(const Scratch& s, const Grids& gr, const uint8_t* c, uint64_t c_bytes,
                       MulScalar k, uint8_t* out, uint64_t out_cap, uint32_t epoch,
                       hoszp_result* res, hipStream_t st);
+// Hadamard product (out: the product stream) or covariance (value in res).
+hipError_t launch_bivar(const Scratch& s, const Grids& gr, bool covariance, const uint8_t* a,
+                        uint64_t a_bytes, const uint8_t* b, uint64_t b_bytes, uint8_t* out,
+                        uint64_t out_cap, uint32_t epoch, hoszp_result* res, hipStream_t st);
 hipError_t launch_f32_unary(const Grids& gr, int op, const float* x, const float* y2, double s,
                             float* out, uint64_t n, hipStream_t st);
 hipError_t launch_f32_reduce(const Scratch& s, const Grids& gr, const float* x, uint64_t n,

@@ -39,10 +39,10 @@ constexpr int kCompressThreads = 1024;
 constexpr int kMulThreads = 1024;
 constexpr int kAddThreads = 1024;
 
-enum { kMean = 0, kVariance = 1, kDecompress = 2 };
+enum { kMean = 0, kVariance = 1, kDecompress = 2, kBlockMean = 3 };
 // context counters (Scratch::ctrl) and accumulators (Scratch::acc)
 enum { C_TICKET = 0, C_DONE = 1, C_WIDTHS = 2 /* 2, 3 */, C_STATUS = 4 };
-enum { A_S = 0, A_QLO = 1, A_QHI = 2, A_WSUM = 3, A_OUT = 4 };
+enum { A_S = 0, A_QLO = 1, A_QHI = 2, A_WSUM = 3, A_OUT = 4, A_CONST = 5, A_SB = 6 };
 
 // ------------------------------------------------------------------ helpers
 
@@ -1061,10 +1061,11 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch(BatchParams p) {
 struct DecodeParams {
   const uint8_t* c;
   uint64_t c_bytes;
-  float* x;
-  uint64_t n_cap;
+  float* x;        // kDecompress: output values
+  uint64_t n_cap;  // kDecompress: capacity of x; kBlockMean: capacity of means
   Scratch s;
   hoszp_result* res;
+  double* means;   // kBlockMean: one mean per block
 };
 
 // sum over the set bits b of a 32-bit word of (b + 1)
@@ -1292,6 +1293,7 @@ __global__ void __launch_bounds__(decode_threads(MODE))
   Layout g;
   uint32_t err = read_header(p.c, p.c_bytes, g);
   if (!err && MODE == kDecompress && p.n_cap < g.n) err = ST_CAPACITY;
+  if (!err && MODE == kBlockMean && p.n_cap < g.nb) err = ST_CAPACITY;
   if (tid == 0 && blockIdx.x == 0) latch(p.s, err);
   const uint64_t nwt = err ? 0 : g.nwtiles;
   const uint8_t* W = p.c + g.off_w;
@@ -1303,7 +1305,7 @@ __global__ void __launch_bounds__(decode_threads(MODE))
   const double two_eb = 2.0 * g.eb;
   int64_t acc_s = 0;
   uint64_t acc_ql = 0, acc_qh = 0;
-  uint32_t bad = 0;
+  uint32_t bad = 0, nconst = 0;
   const uint64_t stride = uint64_t(gridDim.x) * (NT / 64);
   const uint64_t wt0 = uint64_t(blockIdx.x) * (NT / 64) + wave;
   MetaA a1, a2;
@@ -1358,7 +1360,7 @@ __global__ void __launch_bounds__(decode_threads(MODE))
 #pragma unroll
           for (int j = 0; j < 32; ++j) keep32[j] = 0;
         }
-      } else if (MODE == kMean) {
+      } else if (MODE == kMean || MODE == kBlockMean) {
         const uint32_t signs = sub == 0 ? (sw & 0x7fffffffu) : sw;  // slot 0: the outlier
         int32_t d1;
         E = w <= 16 ? mean_fast<true>(sp, w, signs, sub == 0, d1)
@@ -1430,6 +1432,16 @@ __global__ void __launch_bounds__(decode_threads(MODE))
           for (uint32_t t = 0; 4 * q + t < valid; ++t) p.x[e0 + 4 * q + t] = vv[t];
         }
       }
+    } else if (MODE == kBlockMean) {
+      // block sum = sum over the block's segments (consecutive lanes) of the
+      // segment sums cnt * carry + E; slot 0's lane writes the block's mean
+      int64_t bs = cnt > 0 ? int64_t(cnt) * carry + E : 0;
+      acc_s += bs;
+      for (uint32_t m = 1; m < g.spb; m <<= 1) bs += __shfl_xor(bs, int(m), 64);
+      if (cnt > 0 && sub == 0) {
+        p.means[blk] = (double(bs) / double(blen)) * two_eb;
+        nconst += w == 0 ? 1u : 0u;
+      }
     } else if (cnt > 0) {
       // bins of the segment: carry + e_j over its cnt valid slots
       acc_s += int64_t(cnt) * carry + E;
@@ -1447,6 +1459,11 @@ __global__ void __launch_bounds__(decode_threads(MODE))
   }
   latch(p.s, bad);
   double value = 0.0;
+  if (MODE == kBlockMean) {
+    nconst = wave_sum32(nconst);
+    if (lane == 0 && nconst) atomicAdd(reinterpret_cast<unsigned long long*>(&p.s.acc[A_CONST]),
+                                       (unsigned long long)nconst);
+  }
   if (MODE != kDecompress) {
     wg_sum_s_q<NT>(acc_s, acc_ql, acc_qh, s_rs, s_rl, s_rh);
     if (tid == 0) {
@@ -1465,7 +1482,8 @@ __global__ void __launch_bounds__(decode_threads(MODE))
     const int64_t S_all = int64_t(ld_dev(&p.s.acc[A_S]));
     double mean = 0.0, var = 0.0;
     mean_variance(g.n, g.eb, S_all, ld_dev(&p.s.acc[A_QLO]), ld_dev(&p.s.acc[A_QHI]), mean, var);
-    value = MODE == kMean ? mean : var;
+    value = MODE == kVariance ? var : mean;
+    if (MODE == kBlockMean) p.res->count = ld_dev(&p.s.acc[A_CONST]);
   }
   publish(p.s, p.res, 0, value);
 }
@@ -2083,6 +2101,305 @@ __global__ void __launch_bounds__(NT) k_mul(MulParams p) {
   if (finish_arrive(&p.s.ctrl[C_DONE], &s_flag)) publish(p.s, p.res, ld_dev(&p.s.acc[A_OUT]), 0.0);
 }
 
+// ------------------------------------------ bivariate: Hadamard, covariance
+
+struct BivarParams {
+  const uint8_t* a;
+  uint64_t a_bytes;
+  const uint8_t* b;
+  uint64_t b_bytes;
+  uint8_t* out;  // Hadamard only
+  uint64_t out_cap;
+  Scratch s;
+  uint32_t epoch;
+  hoszp_result* res;
+};
+
+enum { kHadamard = 0, kCovariance = 1 };
+constexpr int kBivarThreads = 512;
+
+// floor(2 eps P + 1/2) for an integer P (|P| < 2^62) in exact integer
+// arithmetic, with 2 eps = M 2^-sh (M < 2^53): the 128-bit product M |P|,
+// the rounding half 2^(sh-1) (minus one for negative P, so that the shift
+// rounds the magnitude towards the floor of the signed value), a shift.
+// ST_RANGE when the result leaves the bin range.
+__device__ __forceinline__ int32_t product_bin(int64_t P, uint64_t M, int sh, uint32_t& bad) {
+  if (P == 0) return 0;
+  if (sh <= 0) {  // 2 eps >= 2^52: any non-zero product is far out of range
+    bad |= ST_RANGE;
+    return 0;
+  }
+  if (sh > 120) return 0;  // |2 eps P| < 2^-5
+  const bool neg = P < 0;
+  const uint64_t a = neg ? 0u - uint64_t(P) : uint64_t(P);
+  const unsigned __int128 t = (unsigned __int128)M * a;  // < 2^115
+  const unsigned __int128 r =
+      (t + ((unsigned __int128)1 << (sh - 1)) - (neg ? 1u : 0u)) >> sh;
+  if (r > (unsigned __int128)kBinMax) {
+    bad |= ST_RANGE;
+    return 0;
+  }
+  return neg ? -int32_t(uint32_t(r)) : int32_t(uint32_t(r));
+}
+
+// In-segment prefixes (modulo 2^32) of a staged segment's deltas into r[32];
+// returns the segment's delta total.  Also checks, when the outlier and width
+// allow it, that every bin is a valid int32 bin (ST_FORMAT otherwise).
+__device__ __forceinline__ int64_t segment_prefixes(const uint32_t* sp, uint32_t w, uint32_t sw,
+                                                    uint32_t sub, uint32_t cnt, int32_t* r) {
+  int64_t D = 0;
+  if (cnt == 32 && w <= 20) {
+    if (w == 0) {
+#pragma unroll
+      for (int j = 0; j < 32; ++j) r[j] = 0;
+    } else {
+      D = w <= 16 ? prefix_fast<true>(sp, w, sw, sub == 0, r) : prefix_fast<false>(sp, w, sw, sub == 0, r);
+    }
+  } else if (cnt > 0) {
+    int64_t E = 0;
+    unsigned __int128 E2w = 0;
+    D = decode_generic<true, int32_t>(sp, sw, w, sub, cnt, E, E2w, r);
+  } else {
+#pragma unroll
+    for (int j = 0; j < 32; ++j) r[j] = 0;
+  }
+  return D;
+}
+
+__device__ __forceinline__ void check_bins(const uint32_t* sp, uint32_t sw, uint32_t w, uint32_t sub,
+                                           uint32_t cnt, int64_t outlier, int64_t carry,
+                                           uint64_t blen, uint32_t& bad) {
+  if (cnt > 0 && !bins_surely_in_range(outlier, blen, w)) {
+    int64_t e = 0;
+    for (int j = 0; j < int(cnt); ++j) {
+      if (w && !(j == 0 && sub == 0)) e += seg_delta(sp, sw, w, j);
+      const int64_t bin = carry + e;
+      if (bin < -kBinMax || bin > kBinMax) bad |= ST_FORMAT;
+    }
+  }
+}
+
+// Bivariate operations on two streams of equal n and block size (Sec. V-C,
+// V-D), one tile of NT segments per workgroup: both operands' bins are
+// decoded (payloads staged one after the other in one LDS buffer, A's bins
+// held in registers), then
+//   kHadamard:   bins floor(2 eps q_A q_B + 1/2) re-encoded with the output
+//                look-back, as scalar multiplication does (equal eps needed);
+//   kCovariance: exact sums S_A, S_B (int64) and P = sum q_A q_B (128-bit),
+//                and the last workgroup forms the population covariance.
+template <int MODE, int NT>
+__global__ void __launch_bounds__(NT) k_bivar(BivarParams p) {
+  __shared__ uint32_t s_pay[NT * 32 + 2];
+  __shared__ uint32_t s_tmp[NT / 64];
+  __shared__ uint64_t s_ticket, s_base_a, s_base_b;
+  __shared__ uint32_t s_flag;
+  __shared__ LbShared<NT> s_lb;
+  __shared__ int64_t s_rs[NT / 64];
+  __shared__ uint64_t s_rl[NT / 64], s_rh[NT / 64];
+  const int tid = threadIdx.x;
+  Layout g, gb;
+  uint32_t err = read_header(p.a, p.a_bytes, g);
+  if (!err) err = read_header(p.b, p.b_bytes, gb);
+  if (!err && (g.n != gb.n || g.L != gb.L ||
+               (MODE == kHadamard && __double_as_longlong(g.eb) != __double_as_longlong(gb.eb))))
+    err = ST_MISMATCH;
+  if (MODE == kHadamard && !err && p.out_cap < bound_bytes(g.n, g.L)) err = ST_CAPACITY;
+  if (tid == 0 && blockIdx.x == 0) latch(p.s, err);
+  const uint64_t ntiles = err ? 0 : (g.nseg + NT - 1) / NT;
+  // 2 eps = M 2^-sh from its binary64 fields (2 eps is finite and > 0)
+  const uint64_t eb_bits = uint64_t(__double_as_longlong(2.0 * g.eb));
+  const uint32_t ex = uint32_t(eb_bits >> 52) & 0x7ffu;
+  const uint64_t M = (eb_bits & ((uint64_t(1) << 52) - 1)) | (ex ? uint64_t(1) << 52 : 0u);
+  const int sh = ex ? 1075 - int(ex) : 1074;
+  const uint32_t* Sa = reinterpret_cast<const uint32_t*>(p.a + g.off_s);
+  const uint32_t* Sb = reinterpret_cast<const uint32_t*>(p.b + gb.off_s);
+  const int32_t* Oa = reinterpret_cast<const int32_t*>(p.a + g.off_o);
+  const int32_t* Ob = reinterpret_cast<const int32_t*>(p.b + gb.off_o);
+  const uint32_t* Pa = reinterpret_cast<const uint32_t*>(p.a + g.off_p);
+  const uint32_t* Pb = reinterpret_cast<const uint32_t*>(p.b + gb.off_p);
+  int64_t acc_a = 0, acc_b = 0;
+  uint64_t acc_pl = 0, acc_ph = 0;  // 128-bit two's complement sum of q_A q_B
+  uint32_t next = 0;
+  if (tid == 0) next = atomicAdd(&p.s.ctrl[C_TICKET], 1u);
+  for (;;) {
+    if (tid == 0) s_ticket = next;
+    __syncthreads();
+    const uint64_t tile = uni64(s_ticket);
+    if (tile >= ntiles) break;
+    if (tid < 64) {
+      const uint64_t v = tile_offset(p.s.idx[0], (NT / kWaveSegs) * tile);
+      if (tid == 0) s_base_a = v;
+    } else if (tid < 128) {
+      const uint64_t v = tile_offset(p.s.idx[1], (NT / kWaveSegs) * tile);
+      if (tid == 64) s_base_b = v;
+    }
+    const uint64_t seg = tile * NT + tid;
+    const bool active = seg < g.nseg;
+    const uint64_t blk = (seg >> g.spb_log2);
+    const uint32_t sub = uint32_t(seg & (g.spb - 1));
+    uint64_t blen = 0;
+    const uint32_t cnt = active ? seg_count(g, blk, sub, blen) : 0u;
+    const uint64_t mblk = active ? blk : 0, mseg = active ? seg : 0;
+    const int32_t oa32 = Oa[mblk], ob32 = Ob[mblk];
+    const uint32_t wa8 = p.a[g.off_w + mblk], wb8 = p.b[gb.off_w + mblk];
+    const uint32_t swa8 = Sa[mseg], swb8 = Sb[mseg];
+    uint32_t bad = 0;
+    uint32_t wa = active ? wa8 : 0u, wb = active ? wb8 : 0u;
+    if (wa > 32 || wb > 32) {
+      bad |= ST_FORMAT;
+      wa = wa > 32 ? 0u : wa;
+      wb = wb > 32 ? 0u : wb;
+    }
+    static_assert(NT * 32 < 65536, "tile word counts must fit 16 bits");
+    uint32_t tw2;
+    const uint32_t off2 = wg_scan<NT>(wa | (wb << 16), tw2, s_tmp);  // its barriers publish the bases
+    const uint32_t off_a = off2 & 0xffffu, off_b = off2 >> 16;
+    const uint32_t tw_a = tw2 & 0xffffu, tw_b = tw2 >> 16;
+    const uint64_t base_a = uni64(s_base_a), base_b = uni64(s_base_b);
+    const bool fits_a = base_a + tw_a <= g.payload_bytes / 4;
+    const bool fits_b = base_b + tw_b <= gb.payload_bytes / 4;
+    if (!fits_a || !fits_b) bad |= ST_FORMAT;  // then nothing is read
+    const int64_t oa = active ? oa32 : 0, ob = active ? ob32 : 0;
+    const uint32_t swa = (cnt > 0 && wa) ? bswap32(swa8) : 0u;
+    const uint32_t swb = (cnt > 0 && wb) ? bswap32(swb8) : 0u;
+    // operand A: stage, in-segment prefixes, carry
+    stage_words<NT, false>(s_pay, Pa + base_a, fits_a ? tw_a : 0u, nullptr, 0u);
+    __syncthreads();
+    int32_t ra[32];
+    const int64_t Da = segment_prefixes(&s_pay[1 + off_a], wa, swa, sub, cnt, ra);
+    const int64_t carry_a = oa + block_excl(Da, g.spb);
+    check_bins(&s_pay[1 + off_a], swa, wa, sub, cnt, oa, carry_a, blen, bad);
+    __syncthreads();  // every lane is done reading A
+    // operand B
+    stage_words<NT, false>(s_pay, Pb + base_b, fits_b ? tw_b : 0u, nullptr, 0u);
+    __syncthreads();
+    int32_t rb[32];
+    const int64_t Db = segment_prefixes(&s_pay[1 + off_b], wb, swb, sub, cnt, rb);
+    const int64_t carry_b = ob + block_excl(Db, g.spb);
+    check_bins(&s_pay[1 + off_b], swb, wb, sub, cnt, ob, carry_b, blen, bad);
+    const uint32_t ca = uint32_t(carry_a), cb = uint32_t(carry_b);
+    if (MODE == kCovariance) {
+      int64_t sa = 0, sb = 0;
+      uint64_t pl = 0, ph = 0;
+#pragma unroll
+      for (int j = 0; j < 32; ++j) {
+        if (uint32_t(j) < cnt) {
+          const int32_t qa = int32_t(ca + uint32_t(ra[j])), qb = int32_t(cb + uint32_t(rb[j]));
+          const int64_t prod = int64_t(qa) * int64_t(qb);
+          sa += qa;
+          sb += qb;
+          const uint64_t nl = pl + uint64_t(prod);
+          ph += (prod < 0 ? ~uint64_t(0) : 0u) + (nl < pl ? 1u : 0u);
+          pl = nl;
+        }
+      }
+      acc_a += sa;
+      acc_b += sb;
+      const uint64_t nl = acc_pl + pl;
+      acc_ph += ph + (nl < acc_pl ? 1u : 0u);
+      acc_pl = nl;
+      latch(p.s, bad);
+      if (tid == 0) next = atomicAdd(&p.s.ctrl[C_TICKET], 1u);
+      __syncthreads();  // every lane is done reading B before the next tile stages
+      continue;
+    }
+    // Hadamard: product bins, their deltas, re-encode
+    uint32_t mag[32];
+    uint32_t sgn = 0, mx = 0;
+    int32_t z0 = 0, zp = 0;
+#pragma unroll
+    for (int j = 0; j < 32; ++j) {
+      uint32_t m = 0;
+      if (uint32_t(j) < cnt) {
+        const int32_t qa = int32_t(ca + uint32_t(ra[j])), qb = int32_t(cb + uint32_t(rb[j]));
+        const int32_t z = product_bin(int64_t(qa) * int64_t(qb), M, sh, bad);
+        if (j == 0) {
+          z0 = z;
+        } else {
+          bool neg = false;
+          m = delta_mag(z, zp, neg);
+          sgn |= uint32_t(neg) << (31 - j);
+        }
+        zp = z;
+      }
+      mag[j] = m;
+      mx = max(mx, m);
+    }
+    // slot 0's delta needs the last product bin of the previous segment of
+    // the same block (a segment with valid slots after the first always
+    // follows a full segment)
+    const int32_t prev = __shfl_up(zp, 1, 64);
+    int32_t outlier_z = 0;
+    if (cnt > 0) {
+      if (sub == 0) {
+        outlier_z = z0;
+      } else {
+        bool neg = false;
+        mag[0] = delta_mag(z0, prev, neg);
+        sgn |= uint32_t(neg) << 31;
+        mx = max(mx, mag[0]);
+      }
+    }
+    latch(p.s, bad);
+    mx = block_max(mx, g.spb);
+    const uint32_t wz = bitlen32(mx);
+    uint32_t tw_z;
+    const uint32_t off_z = wg_scan<NT>(wz, tw_z, s_tmp);  // barriers: all threads done reading B
+    lb_publish(p.s.st_out, tile, tw_z, p.epoch);
+    if (wz > 0) pack32(&s_pay[off_z], mag, wz);
+    if (active) {
+      if (sub == 0) {
+        p.out[g.off_w + blk] = uint8_t(wz);
+        reinterpret_cast<int32_t*>(p.out + g.off_o)[blk] = outlier_z;
+      }
+      reinterpret_cast<uint32_t*>(p.out + g.off_s)[seg] = bswap32(sgn);
+    }
+    const uint64_t base_z = lb_wait<NT>(p.s.st_out, tile, tw_z, p.epoch, s_lb);
+    if (tid == 0) next = atomicAdd(&p.s.ctrl[C_TICKET], 1u);
+    __syncthreads();
+    uint32_t* Pz = reinterpret_cast<uint32_t*>(p.out + g.off_p) + base_z;
+    for (uint32_t k = tid; k < tw_z; k += NT) Pz[k] = bswap32(s_pay[k]);
+    if (tid == 0 && tile == ntiles - 1) {
+      const uint64_t payload = 4 * (base_z + tw_z);
+      write_header(p.out, g, payload);
+      st_dev(&p.s.acc[A_OUT], g.off_p + payload);
+    }
+    __syncthreads();
+  }
+  if (MODE == kCovariance) {
+    int64_t dummy_s = acc_b;
+    uint64_t zl = 0, zh = 0;
+    wg_sum_s_q<NT>(acc_a, acc_pl, acc_ph, s_rs, s_rl, s_rh);
+    wg_sum_s_q<NT>(dummy_s, zl, zh, s_rs, s_rl, s_rh);
+    if (tid == 0) {
+      atomicAdd(reinterpret_cast<unsigned long long*>(&p.s.acc[A_S]), (unsigned long long)acc_a);
+      atomicAdd(reinterpret_cast<unsigned long long*>(&p.s.acc[A_SB]), (unsigned long long)dummy_s);
+      const uint64_t old = atomicAdd(reinterpret_cast<unsigned long long*>(&p.s.acc[A_QLO]),
+                                     (unsigned long long)acc_pl);
+      const uint64_t carry_out = (old + acc_pl < old) ? 1u : 0u;
+      atomicAdd(reinterpret_cast<unsigned long long*>(&p.s.acc[A_QHI]),
+                (unsigned long long)(acc_ph + carry_out));
+    }
+    if (!finish_arrive(&p.s.ctrl[C_DONE], &s_flag)) return;
+    double value = 0.0;
+    if (tid == 0 && !err) {
+      // n P - S_A S_B exactly in 128 bits (|.| < 2^126), then
+      // ((double)m / n / n) (2 eps_A)(2 eps_B)
+      const __int128 P = (__int128)(((unsigned __int128)ld_dev(&p.s.acc[A_QHI]) << 64) |
+                                    ld_dev(&p.s.acc[A_QLO]));
+      const __int128 SA = int64_t(ld_dev(&p.s.acc[A_S])), SB = int64_t(ld_dev(&p.s.acc[A_SB]));
+      const __int128 m = __int128(g.n) * P - SA * SB;
+      const unsigned __int128 am = m < 0 ? (unsigned __int128)(-m) : (unsigned __int128)m;
+      const double mag_d = u128_to_double(uint64_t(am >> 64), uint64_t(am));
+      const double md = m < 0 ? -mag_d : mag_d;
+      value = ((md / double(g.n)) / double(g.n)) * ((2.0 * g.eb) * (2.0 * gb.eb));
+    }
+    publish(p.s, p.res, 0, value);
+    return;
+  }
+  if (finish_arrive(&p.s.ctrl[C_DONE], &s_flag)) publish(p.s, p.res, ld_dev(&p.s.acc[A_OUT]), 0.0);
+}
+
 // ---------------------------------------------------- float32 workflow ops
 
 __global__ void __launch_bounds__(kThreads) k_f32_map(int op, const float* x, const float* y,
@@ -2220,6 +2537,16 @@ hipError_t launch_reduce(const Scratch& s, const Grids& gr, const uint8_t* c, ui
   return hipGetLastError();
 }
 
+hipError_t launch_block_means(const Scratch& s, const Grids& gr, const uint8_t* c,
+                              uint64_t c_bytes, double* means, uint64_t means_cap,
+                              hoszp_result* res, hipStream_t st) {
+  hipError_t e = launch_widths(s, gr, 0, c, c_bytes, st);
+  if (e != hipSuccess) return e;
+  DecodeParams p{c, c_bytes, nullptr, means_cap, s, res, means};
+  hipLaunchKernelGGL(k_decode<kBlockMean>, dim3(gr.reduce), dim3(kReduceThreads), 0, st, p);
+  return hipGetLastError();
+}
+
 hipError_t launch_negate(const Scratch& s, const Grids& gr, const uint8_t* c, uint64_t c_bytes,
                          uint8_t* out, uint64_t out_cap, hoszp_result* res, hipStream_t st) {
   NegateParams p{c, c_bytes, out, out_cap, s, res, 0.0, 0, 0};
@@ -2258,6 +2585,20 @@ hipError_t launch_mul(const Scratch& s, const Grids& gr, const uint8_t* c, uint6
   if (e != hipSuccess) return e;
   MulParams p{c, c_bytes, out, out_cap, k, s, epoch, res};
   hipLaunchKernelGGL(k_mul<kMulThreads>, dim3(gr.mul), dim3(kMulThreads), 0, st, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_bivar(const Scratch& s, const Grids& gr, bool covariance, const uint8_t* a,
+                        uint64_t a_bytes, const uint8_t* b, uint64_t b_bytes, uint8_t* out,
+                        uint64_t out_cap, uint32_t epoch, hoszp_result* res, hipStream_t st) {
+  hipError_t e = launch_widths(s, gr, 0, a, a_bytes, st);
+  if (e == hipSuccess) e = launch_widths(s, gr, 1, b, b_bytes, st);
+  if (e != hipSuccess) return e;
+  BivarParams p{a, a_bytes, b, b_bytes, out, out_cap, s, epoch, res};
+  if (covariance)
+    hipLaunchKernelGGL((k_bivar<kCovariance, kBivarThreads>), dim3(gr.bivar), dim3(kBivarThreads), 0, st, p);
+  else
+    hipLaunchKernelGGL((k_bivar<kHadamard, kBivarThreads>), dim3(gr.bivar), dim3(kBivarThreads), 0, st, p);
   return hipGetLastError();
 }
 
@@ -2304,8 +2645,13 @@ hipError_t query_grids(Grids& gr, int num_cus) {
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&r, k_decode<kMean>, kReduceThreads, 0);
   if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_add<kAddThreads, false>, kAddThreads, 0);
   if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&m, k_mul<kMulThreads>, kMulThreads, 0);
+  int bv = 0;
+  if (e == hipSuccess)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&bv, k_bivar<kHadamard, kBivarThreads>,
+                                                     kBivarThreads, 0);
   if (e != hipSuccess) return e;
   auto clampg = [&](int occ) { return num_cus * (occ < 1 ? 1 : occ); };
+  gr.bivar = clampg(bv);
   gr.compress = clampg(c);
   gr.decode = clampg(d);
   gr.reduce = clampg(r);

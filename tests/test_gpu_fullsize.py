@@ -123,6 +123,9 @@ def test_fullsize_homomorphic_ops(fields, rel):
                  lambda i, j: ref.sub(ref.compress(a[i:j], eb, L), ref.compress(b[i:j], eb, L)))
     check_slices(hz.scalar_add(cb, -0.37).cpu().numpy(), n, slices,
                  lambda i, j: ref.scalar_add(ref.compress(b[i:j], eb, L), -0.37))
+    check_slices(hz.hadamard(ca, cb).cpu().numpy(), n, slices,
+                 lambda i, j: ref.hadamard(ref.compress(a[i:j], eb, L),
+                                           ref.compress(b[i:j], eb, L)))
 
 
 # ------------------------------------------- 1800 x 3600 climate-like steps
@@ -157,6 +160,9 @@ def test_fullsize_climate_steps(climate, block):
         assert np.array_equal(hz.scalar_add(c, float(s[t])).cpu().numpy(),
                               ref.scalar_add(xc, float(s[t]))), f"scalar add step {t}"
         assert abs(hz.std(c) - ref.std(xc)) <= 1e-12 * ref.std(xc)
+        bm, bc = hz.block_means(c)
+        wm, wc = ref.block_means(xc)
+        assert bc == wc and np.array_equal(bm.cpu().numpy(), wm), f"block means step {t}"
         if prev is not None:
             # pairwise step add: both operands at this step's eb (add needs equal eb)
             pc = ref.compress(prev, eb, block)
@@ -164,4 +170,9 @@ def test_fullsize_climate_steps(climate, block):
             assert np.array_equal(got.cpu().numpy(), ref.add(pc, xc)), f"add steps {t-1}+{t}"
             got = hz.sub(c, hz.compress(torch.from_numpy(prev).to(dev), eb, block))
             assert np.array_equal(got.cpu().numpy(), ref.sub(xc, pc)), f"sub steps {t}-{t-1}"
+            gp = hz.compress(torch.from_numpy(prev).to(dev), eb, block)
+            assert np.array_equal(hz.hadamard(gp, c).cpu().numpy(), ref.hadamard(pc, xc)), \
+                f"hadamard steps {t-1}*{t}"
+            cv = ref.covariance(pc, xc)
+            assert abs(hz.covariance(gp, c) - cv) <= 1e-12 * abs(cv)
         prev = x

@@ -1,6 +1,8 @@
 """GPU parity (through the C ABI) of the remaining Table II operations with
 the CPU oracle: scalar addition and subtraction (Sec. V-A, workflow 1),
-element-wise subtraction (Sec. V-C), standard deviation (Sec. V-B).
+element-wise subtraction and the Hadamard product (Sec. V-C), standard
+deviation and block-wise means with constant-block counts (Sec. V-B),
+covariance (Sec. V-D).
 
 Streams must be byte-identical to the oracle's, doubles equal to 1e-12
 relative; sizes span several 32768-slot encoder tiles with ragged tails and
@@ -171,3 +173,107 @@ def test_std(dev, L):
         want = ref.std(xc)
         got = hz.std(gpu(xc, dev))
         assert got == want or abs(got - want) <= 1e-12 * abs(want), (got, want)
+
+
+# ------------------------------------------------ Hadamard and covariance
+
+PAIR_CASES = [(1, 32), (33, 64), (5000, 32), (70001, 128), (300007, 256), (1500001, 32)]
+
+
+@pytest.mark.parametrize("n,L", PAIR_CASES)
+def test_hadamard(dev, n, L):
+    print(f"case hadamard n={n} L={L}", flush=True)
+    x = walk(n, 21 + n % 7, scale=2.0)
+    y = walk(n, 22 + n % 5, scale=2.0)
+    x[n // 2:n // 2 + 3 * L] = 0.0                     # zero products, constant blocks
+    for rel in (1e-2, 1e-3):
+        eb = synth.rel_eb(x, rel)
+        xc, yc = ref.compress(x, eb, L), ref.compress(y, eb, L)
+        a, b = gpu(xc, dev), gpu(yc, dev)
+        want = ref.hadamard(xc, yc)
+        assert np.array_equal(host(hz.hadamard(a, b)), want), rel
+        assert np.array_equal(host(hz.hadamard(b, a)), want), rel
+
+
+def test_hadamard_exact_cases(dev):
+    """eps = 1/2 (decoded values are the bins: the product is exact), eps =
+    1/4 (every odd product is a tie, rounded up), eps = 2^-1074-ish tiny and
+    large products (range), mismatched operands."""
+    rng = np.random.default_rng(6)
+    qa = rng.integers(-40000, 40001, 90001).astype(np.int32)
+    qb = rng.integers(-40000, 40001, 90001).astype(np.int32)
+    for eb, L in ((0.5, 32), (0.25, 64), (0.375, 128), (1e-3, 256)):
+        ac, bc = ref.encode_bins(qa, eb, L), ref.encode_bins(qb, eb, L)
+        assert np.array_equal(host(hz.hadamard(gpu(ac, dev), gpu(bc, dev))), ref.hadamard(ac, bc)), eb
+    ac = ref.encode_bins(np.full(100, 70000, np.int32), 0.5, 32)
+    assert err_of(hz.hadamard, gpu(ac, dev), gpu(ac, dev)) == hz.ERR_RANGE
+    tiny = ref.encode_bins(qa[:5000], 2.0**-1060, 32)
+    assert np.array_equal(host(hz.hadamard(gpu(tiny, dev), gpu(tiny, dev))), ref.hadamard(tiny, tiny))
+    x = walk(3000, 5)
+    a = gpu(ref.compress(x, 0.01, 32), dev)
+    for other in (ref.compress(x[:2999], 0.01, 32), ref.compress(x, 0.01, 64),
+                  ref.compress(x, 0.01 * (1 + 2**-52), 32)):
+        assert err_of(hz.hadamard, a, gpu(other, dev)) == hz.ERR_MISMATCH
+
+
+@pytest.mark.parametrize("n,L", PAIR_CASES)
+def test_covariance(dev, n, L):
+    print(f"case covariance n={n} L={L}", flush=True)
+    x = walk(n, 31 + n % 7)
+    y = (0.5 * x + walk(n, 32 + n % 3)).astype(np.float32)
+    ea, eb = synth.rel_eb(x, 1e-3), synth.rel_eb(y, 1e-4)   # different bounds are allowed
+    xc, yc = ref.compress(x, ea, L), ref.compress(y, eb, L)
+    a, b = gpu(xc, dev), gpu(yc, dev)
+    for u, v, uc, vc in ((a, b, xc, yc), (b, a, yc, xc), (a, a, xc, xc)):
+        want = ref.covariance(uc, vc)
+        got = hz.covariance(u, v)
+        assert got == want or abs(got - want) <= 1e-12 * abs(want), (got, want)
+    assert hz.covariance(a, a) == ref.variance(xc) or \
+        abs(hz.covariance(a, a) - ref.variance(xc)) <= 1e-12 * ref.variance(xc)
+
+
+def test_covariance_extreme_bins(dev):
+    """Bins near +-2^31 make q_A q_B ~ 2^62 and the 128-bit sums carry."""
+    rng = np.random.default_rng(9)
+    qa = rng.integers(-BIN_MAX, BIN_MAX + 1, 200003).astype(np.int32)
+    qb = rng.integers(-BIN_MAX, BIN_MAX + 1, 200003).astype(np.int32)
+    qb[::3] = qa[::3]
+    for L in BLOCKS:
+        ac, bc = ref.encode_bins(qa, 0.5, L), ref.encode_bins(qb, 0.25, L)
+        want = ref.covariance(ac, bc)
+        got = hz.covariance(gpu(ac, dev), gpu(bc, dev))
+        assert got == want or abs(got - want) <= 1e-12 * abs(want), (L, got, want)
+    x = walk(1000, 2)
+    a = gpu(ref.compress(x, 0.01, 32), dev)
+    for other in (ref.compress(x[:999], 0.01, 32), ref.compress(x, 0.01, 64)):
+        assert err_of(hz.covariance, a, gpu(other, dev)) == hz.ERR_MISMATCH
+
+
+# ------------------------------------------------------ block-wise means
+
+@pytest.mark.parametrize("n,L", [(1, 32), (100, 64), (70001, 32), (300007, 128), (1048576, 256),
+                                 (2000003, 32)])
+def test_block_means(dev, n, L):
+    print(f"case block means n={n} L={L}", flush=True)
+    x = walk(n, 41 + n % 11)
+    x[n // 4:n // 4 + 7 * L] = -2.5                 # constant blocks
+    x[n // 2:n // 2 + 2 * L] = 0.0
+    eb = synth.rel_eb(x, 1e-2)
+    xc = ref.compress(x, eb, L)
+    want, want_const = ref.block_means(xc)
+    got, got_const = hz.block_means(gpu(xc, dev))
+    assert got_const == want_const
+    assert np.array_equal(host(got), want)
+    res = hz.new_result(dev)
+    out = torch.empty(want.size, dtype=torch.float64, device=dev)
+    ctx = hz.context(0)
+    assert hz._lib().hoszp_block_means_async(ctx.handle, hz._ptr(gpu(xc, dev)), xc.size,
+                                             hz._ptr(out), out.numel(), hz._ptr(res),
+                                             hz._stream(None)) == 0
+    r = hz.read_result(res)
+    assert r["code"] == 0 and r["count"] == want_const and r["value"] == ref.mean(xc)
+    small = torch.empty(max(want.size - 1, 0), dtype=torch.float64, device=dev)
+    if want.size > 1:
+        with pytest.raises(hz.HoszpError) as e:
+            hz.block_means(gpu(xc, dev), out=small)
+        assert e.value.code == hz.ERR_CAPACITY
