@@ -486,6 +486,48 @@ def mul_async(c, s, out, res, ctx=None, stream=None, c_bytes=None):
                                   _nbytes(out), _ptr(res), _stream(stream)), "mul_async")
 
 
+def sub_async(a, b, out, res, ctx=None, stream=None, a_bytes=None, b_bytes=None):
+    ctx = ctx or context(a.device.index)
+    _check(_lib().hoszp_sub_async(ctx.handle, _ptr(a), a_bytes or _nbytes(a), _ptr(b),
+                                  b_bytes or _nbytes(b), _ptr(out), _nbytes(out), _ptr(res),
+                                  _stream(stream)), "sub_async")
+
+
+def hadamard_async(a, b, out, res, ctx=None, stream=None, a_bytes=None, b_bytes=None):
+    ctx = ctx or context(a.device.index)
+    _check(_lib().hoszp_hadamard_async(ctx.handle, _ptr(a), a_bytes or _nbytes(a), _ptr(b),
+                                       b_bytes or _nbytes(b), _ptr(out), _nbytes(out), _ptr(res),
+                                       _stream(stream)), "hadamard_async")
+
+
+def covariance_async(a, b, res, ctx=None, stream=None, a_bytes=None, b_bytes=None):
+    ctx = ctx or context(a.device.index)
+    _check(_lib().hoszp_covariance_async(ctx.handle, _ptr(a), a_bytes or _nbytes(a), _ptr(b),
+                                         b_bytes or _nbytes(b), _ptr(res), _stream(stream)),
+           "covariance_async")
+
+
+def scalar_add_async(c, s, out, res, ctx=None, stream=None, c_bytes=None):
+    ctx = ctx or context(c.device.index)
+    _check(_lib().hoszp_scalar_add_async(ctx.handle, _ptr(c), c_bytes or _nbytes(c), float(s),
+                                         _ptr(out), _nbytes(out), _ptr(res), _stream(stream)),
+           "scalar_add_async")
+
+
+def scalar_sub_async(c, s, out, res, ctx=None, stream=None, c_bytes=None):
+    ctx = ctx or context(c.device.index)
+    _check(_lib().hoszp_scalar_sub_async(ctx.handle, _ptr(c), c_bytes or _nbytes(c), float(s),
+                                         _ptr(out), _nbytes(out), _ptr(res), _stream(stream)),
+           "scalar_sub_async")
+
+
+def block_means_async(c, out, res, ctx=None, stream=None, c_bytes=None):
+    ctx = ctx or context(c.device.index)
+    _check(_lib().hoszp_block_means_async(ctx.handle, _ptr(c), c_bytes or _nbytes(c), _ptr(out),
+                                          out.numel(), _ptr(res), _stream(stream)),
+           "block_means_async")
+
+
 def mean_async(c, res, ctx=None, stream=None, c_bytes=None):
     ctx = ctx or context(c.device.index)
     _check(_lib().hoszp_mean_async(ctx.handle, _ptr(c), c_bytes or _nbytes(c), _ptr(res),

@@ -20,7 +20,6 @@ struct hoszp_ctx {
   void* d_mem;
   hoszp_result* d_res;  // record used by the synchronous entry points
   hoszp_result* h_res;  // pinned host mirror of d_res
-  uint32_t epoch;       // look-back generation, 28 bits, never 0
 };
 
 struct hoszp_batch {
@@ -37,7 +36,6 @@ struct hoszp_batch {
 
 namespace {
 
-constexpr uint32_t kEpochMask = (1u << 28) - 1;
 constexpr uint32_t kMaxTiles = uint32_t((hz::kMaxN + hz::kMinTileSegs * 32ull) / (hz::kMinTileSegs * 32ull) + 1);
 constexpr uint32_t kMaxPart = 4096;
 
@@ -65,20 +63,6 @@ inline bool aligned(const void* p, uintptr_t a) { return (reinterpret_cast<uintp
 inline bool overlap(const void* a, size_t na, const void* b, size_t nb) {
   const uintptr_t pa = reinterpret_cast<uintptr_t>(a), pb = reinterpret_cast<uintptr_t>(b);
   return na && nb && pa < pb + nb && pb < pa + na;
-}
-
-// Next look-back generation.  Status words carry the generation, so they never
-// need clearing -- except once every 2^28 - 1 calls when the counter wraps.
-int next_epoch(hoszp_ctx* ctx, hipStream_t st, uint32_t* epoch) {
-  uint32_t e = (ctx->epoch + 1) & kEpochMask;
-  if (e == 0) {
-    e = 1;
-    if (hz::launch_zero64(ctx->s.st_out, ctx->s.max_tiles, st) != hipSuccess)
-      return HOSZP_ERR_DEVICE;
-  }
-  ctx->epoch = e;
-  *epoch = e;
-  return HOSZP_OK;
 }
 
 int device_status(hipError_t e) { return e == hipSuccess ? HOSZP_OK : HOSZP_ERR_DEVICE; }
@@ -227,7 +211,6 @@ int hoszp_ctx_create(int device, hoszp_ctx** out) {
   ctx->d_res = reinterpret_cast<hoszp_result*>(q);
   ctx->s.max_tiles = kMaxTiles;
   ctx->s.max_part = kMaxPart;
-  ctx->epoch = 0;
   if (hipMemset(ctx->d_mem, 0, bytes) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
     (void)hipHostFree(ctx->h_res);
     (void)hipFree(ctx->d_mem);
@@ -273,11 +256,8 @@ int hoszp_compress_async(hoszp_ctx* ctx, const float* d_x, uint64_t n, double eb
   hz::Layout g;
   hz::place(g, n, block, eb);
   const double inv2e = 1.0 / (2.0 * eb);
-  uint32_t epoch;
-  int rc = next_epoch(ctx, st, &epoch);
-  if (rc) return rc;
   return launched(ctx, d_res, st, hz::launch_compress(ctx->s, ctx->grids, d_x, g, inv2e,
-                                           static_cast<uint8_t*>(d_out), epoch, d_res, st));
+                                           static_cast<uint8_t*>(d_out), d_res, st));
 }
 
 int hoszp_compress(hoszp_ctx* ctx, const float* d_x, uint64_t n, double eb, uint32_t block,
@@ -297,12 +277,9 @@ int hoszp_decompress_async(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, floa
   DeviceScope scope(ctx->device);
   if (!scope.ok()) return HOSZP_ERR_DEVICE;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  uint32_t epoch;
-  int rc = next_epoch(ctx, st, &epoch);
-  if (rc) return rc;
   return launched(ctx, d_res, st, hz::launch_decompress(ctx->s, ctx->grids,
                                              static_cast<const uint8_t*>(d_c), c_bytes, d_x,
-                                             n_cap, epoch, d_res, st));
+                                             n_cap, d_res, st));
 }
 
 int hoszp_decompress(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, float* d_x,
@@ -349,12 +326,9 @@ static int add_like(hoszp_ctx* ctx, const void* d_a, size_t a_bytes, const void*
   DeviceScope scope(ctx->device);
   if (!scope.ok()) return HOSZP_ERR_DEVICE;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  uint32_t epoch;
-  int rc = next_epoch(ctx, st, &epoch);
-  if (rc) return rc;
   return launched(ctx, d_res, st, hz::launch_add(ctx->s, ctx->grids, static_cast<const uint8_t*>(d_a),
                                       a_bytes, static_cast<const uint8_t*>(d_b), b_bytes,
-                                      static_cast<uint8_t*>(d_out), out_cap, epoch, d_res, st,
+                                      static_cast<uint8_t*>(d_out), out_cap, d_res, st,
                                       sub));
 }
 
@@ -438,12 +412,9 @@ int hoszp_mul_async(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, double s, v
   DeviceScope scope(ctx->device);
   if (!scope.ok()) return HOSZP_ERR_DEVICE;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  uint32_t epoch;
-  int rc = next_epoch(ctx, st, &epoch);
-  if (rc) return rc;
   return launched(ctx, d_res, st, hz::launch_mul(ctx->s, ctx->grids, static_cast<const uint8_t*>(d_c),
                                       c_bytes, mul_split(s), static_cast<uint8_t*>(d_out),
-                                      out_cap, epoch, d_res, st));
+                                      out_cap, d_res, st));
 }
 
 int hoszp_mul(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, double s, void* d_out,
@@ -476,11 +447,8 @@ static int reduce_async(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, bool va
   DeviceScope scope(ctx->device);
   if (!scope.ok()) return HOSZP_ERR_DEVICE;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  uint32_t epoch;
-  int rc = next_epoch(ctx, st, &epoch);
-  if (rc) return rc;
   return launched(ctx, d_res, st, hz::launch_reduce(ctx->s, ctx->grids, static_cast<const uint8_t*>(d_c),
-                                         c_bytes, variance, epoch, d_res, st));
+                                         c_bytes, variance, d_res, st));
 }
 
 int hoszp_mean_async(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, hoszp_result* d_res,
@@ -523,13 +491,10 @@ int hoszp_hadamard_async(hoszp_ctx* ctx, const void* d_a, size_t a_bytes, const 
   DeviceScope scope(ctx->device);
   if (!scope.ok()) return HOSZP_ERR_DEVICE;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  uint32_t epoch;
-  int rc = next_epoch(ctx, st, &epoch);
-  if (rc) return rc;
   return launched(ctx, d_res, st, hz::launch_bivar(ctx->s, ctx->grids, false,
                                         static_cast<const uint8_t*>(d_a), a_bytes,
                                         static_cast<const uint8_t*>(d_b), b_bytes,
-                                        static_cast<uint8_t*>(d_out), out_cap, epoch, d_res, st));
+                                        static_cast<uint8_t*>(d_out), out_cap, d_res, st));
 }
 
 int hoszp_hadamard(hoszp_ctx* ctx, const void* d_a, size_t a_bytes, const void* d_b,
@@ -548,7 +513,7 @@ int hoszp_covariance_async(hoszp_ctx* ctx, const void* d_a, size_t a_bytes, cons
   return launched(ctx, d_res, st, hz::launch_bivar(ctx->s, ctx->grids, true,
                                         static_cast<const uint8_t*>(d_a), a_bytes,
                                         static_cast<const uint8_t*>(d_b), b_bytes, nullptr, 0,
-                                        0, d_res, st));
+                                        d_res, st));
 }
 
 int hoszp_covariance(hoszp_ctx* ctx, const void* d_a, size_t a_bytes, const void* d_b,

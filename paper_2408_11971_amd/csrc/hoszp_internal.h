@@ -177,13 +177,12 @@ struct Grids {
 // failed launch left an operation half-enqueued.
 hipError_t launch_reset(const Scratch& s, hoszp_result* res, hipStream_t st);
 hipError_t launch_compress(const Scratch& s, const Grids& gr, const float* x, const Layout& g,
-                           double inv2e, uint8_t* out, uint32_t epoch, hoszp_result* res,
-                           hipStream_t st);
+                           double inv2e, uint8_t* out, hoszp_result* res, hipStream_t st);
 hipError_t launch_decompress(const Scratch& s, const Grids& gr, const uint8_t* c,
-                             uint64_t c_bytes, float* x, uint64_t n_cap, uint32_t epoch,
-                             hoszp_result* res, hipStream_t st);
+                             uint64_t c_bytes, float* x, uint64_t n_cap, hoszp_result* res,
+                             hipStream_t st);
 hipError_t launch_reduce(const Scratch& s, const Grids& gr, const uint8_t* c, uint64_t c_bytes,
-                         bool variance, uint32_t epoch, hoszp_result* res, hipStream_t st);
+                         bool variance, hoszp_result* res, hipStream_t st);
 hipError_t launch_negate(const Scratch& s, const Grids& gr, const uint8_t* c, uint64_t c_bytes,
                          uint8_t* out, uint64_t out_cap, hoszp_result* res, hipStream_t st);
 hipError_t launch_block_means(const Scratch& s, const Grids& gr, const uint8_t* c,
@@ -196,14 +195,14 @@ hipError_t launch_shift(const Scratch& s, const Grids& gr, const uint8_t* c, uin
 // Element-wise addition, or subtraction a - b when `sub`.
 hipError_t launch_add(const Scratch& s, const Grids& gr, const uint8_t* a, uint64_t a_bytes,
                       const uint8_t* b, uint64_t b_bytes, uint8_t* out, uint64_t out_cap,
-                      uint32_t epoch, hoszp_result* res, hipStream_t st, bool sub = false);
+                      hoszp_result* res, hipStream_t st, bool sub = false);
 hipError_t launch_mul(const Scratch& s, const Grids& gr, const uint8_t* c, uint64_t c_bytes,
-                      MulScalar k, uint8_t* out, uint64_t out_cap, uint32_t epoch,
-                      hoszp_result* res, hipStream_t st);
+                      MulScalar k, uint8_t* out, uint64_t out_cap, hoszp_result* res,
+                      hipStream_t st);
 // Hadamard product (out: the product stream) or covariance (value in res).
 hipError_t launch_bivar(const Scratch& s, const Grids& gr, bool covariance, const uint8_t* a,
                         uint64_t a_bytes, const uint8_t* b, uint64_t b_bytes, uint8_t* out,
-                        uint64_t out_cap, uint32_t epoch, hoszp_result* res, hipStream_t st);
+                        uint64_t out_cap, hoszp_result* res, hipStream_t st);
 hipError_t launch_f32_unary(const Grids& gr, int op, const float* x, const float* y2, double s,
                             float* out, uint64_t n, hipStream_t st);
 hipError_t launch_f32_reduce(const Scratch& s, const Grids& gr, const float* x, uint64_t n,

@@ -41,7 +41,7 @@ constexpr int kAddThreads = 1024;
 
 enum { kMean = 0, kVariance = 1, kDecompress = 2, kBlockMean = 3 };
 // context counters (Scratch::ctrl) and accumulators (Scratch::acc)
-enum { C_TICKET = 0, C_DONE = 1, C_WIDTHS = 2 /* 2, 3 */, C_STATUS = 4 };
+enum { C_TICKET = 0, C_DONE = 1, C_WIDTHS = 2 /* 2, 3 */, C_STATUS = 4, C_EPOCH = 5 };
 enum { A_S = 0, A_QLO = 1, A_QHI = 2, A_WSUM = 3, A_OUT = 4, A_CONST = 5, A_SB = 6 };
 
 // ------------------------------------------------------------------ helpers
@@ -269,6 +269,25 @@ __device__ __forceinline__ uint64_t wg_scan64(uint64_t v, uint64_t& total, uint6
 
 __device__ __forceinline__ uint64_t lb_word(uint32_t epoch, uint64_t flag, uint64_t v) {
   return (uint64_t(epoch) << 36) | (flag << 34) | (v & kLbValMask);
+}
+
+// Look-back generation of a single-stream encoder launch: one more than the
+// previous launch's, kept in the context's counter word (28 bits, never 0).
+// It lives on the device so that a launch captured in a graph gets a fresh
+// generation at every replay: status words a previous replay published
+// never look valid to the next one.
+__device__ __forceinline__ uint32_t launch_epoch(const Scratch& s) {
+  const uint32_t e = (uni32(ld_dev32(&s.ctrl[C_EPOCH])) + 1u) & (kEpochLimit - 1u);
+  return e ? e : 1u;
+}
+
+// Last workgroup of an encoder launch (whole workgroup): record the launch's
+// generation; before the counter wraps, clear every status word so no word
+// of an earlier launch with the same generation survives.
+__device__ __forceinline__ void retire_epoch(const Scratch& s, uint32_t epoch) {
+  if (epoch == kEpochLimit - 1u)
+    for (uint64_t k = threadIdx.x; k < s.max_tiles; k += blockDim.x) s.st_out[k] = 0;
+  if (threadIdx.x == 0) s.ctrl[C_EPOCH] = epoch;
 }
 
 template <int NT = kThreads>
@@ -706,7 +725,6 @@ struct CompressParams {
   Layout g;
   double eb, inv2e;
   Scratch s;
-  uint32_t epoch;
   hoszp_result* res;
 };
 
@@ -902,6 +920,7 @@ __global__ void __launch_bounds__(NT) k_compress(CompressParams p) {
   const uint64_t ntiles = (g.nseg + NT - 1) / NT;
   uint32_t bad = 0, next = 0;
   BinSums none;
+  const uint32_t epoch = launch_epoch(p.s);
   if (tid == 0) next = atomicAdd(&p.s.ctrl[C_TICKET], 1u);
   for (;;) {
     if (tid == 0) sh.ticket = next;
@@ -909,13 +928,15 @@ __global__ void __launch_bounds__(NT) k_compress(CompressParams p) {
     const uint64_t tile = uni64(sh.ticket);
     if (tile >= ntiles) break;
     const uint64_t words =
-        compress_tile<SPB, false, NT>(p.x, p.out, g, p.eb, p.inv2e, tile, p.s.st_out, p.epoch, sh,
+        compress_tile<SPB, false, NT>(p.x, p.out, g, p.eb, p.inv2e, tile, p.s.st_out, epoch, sh,
                                   bad, none, &p.s.ctrl[C_TICKET], next);
     if (tid == 0 && tile == ntiles - 1) st_dev(&p.s.acc[A_OUT], g.off_p + 4 * words);
   }
   latch(p.s, bad);
-  if (finish_arrive(&p.s.ctrl[C_DONE], &sh.flag))
+  if (finish_arrive(&p.s.ctrl[C_DONE], &sh.flag)) {
+    retire_epoch(p.s, epoch);
     publish(p.s, p.res, ld_dev(&p.s.acc[A_OUT]), 0.0);
+  }
 }
 
 // mean = (S / n) 2 eps and variance = ((n Q - S^2) / n / n) (2 eps)^2 from the
@@ -1687,7 +1708,6 @@ struct AddParams {
   uint8_t* out;
   uint64_t out_cap;
   Scratch s;
-  uint32_t epoch;
   hoszp_result* res;
 };
 
@@ -1719,6 +1739,7 @@ __global__ void __launch_bounds__(NT) k_add(AddParams p) {
   const int32_t* Oa = reinterpret_cast<const int32_t*>(p.a + g.off_o);
   const int32_t* Ob = reinterpret_cast<const int32_t*>(p.b + gb.off_o);
   uint32_t next = 0;
+  const uint32_t epoch = launch_epoch(p.s);
   if (tid == 0) next = atomicAdd(&p.s.ctrl[C_TICKET], 1u);
   for (;;) {
     if (tid == 0) s_ticket = next;
@@ -1890,7 +1911,7 @@ __global__ void __launch_bounds__(NT) k_add(AddParams p) {
     uint32_t tw_z;
     const uint32_t off_z = wg_scan<NT>(w, tw_z, s_tmp);  // barriers: all threads done reading B
     // publish the output tile's size, then pack and store what needs no offset
-    lb_publish(p.s.st_out, tile, tw_z, p.epoch);
+    lb_publish(p.s.st_out, tile, tw_z, epoch);
     if (w > 0) pack32(&s_pay[off_z], mag, w);
     if (active) {
       if (sub == 0) {
@@ -1899,7 +1920,7 @@ __global__ void __launch_bounds__(NT) k_add(AddParams p) {
       }
       reinterpret_cast<uint32_t*>(p.out + g.off_s)[seg] = bswap32(sgn);
     }
-    const uint64_t base_z = lb_wait<NT>(p.s.st_out, tile, tw_z, p.epoch, s_lb);
+    const uint64_t base_z = lb_wait<NT>(p.s.st_out, tile, tw_z, epoch, s_lb);
     if (tid == 0) next = atomicAdd(&p.s.ctrl[C_TICKET], 1u);
     __syncthreads();
     uint32_t* Pz = reinterpret_cast<uint32_t*>(p.out + g.off_p) + base_z;
@@ -1911,7 +1932,10 @@ __global__ void __launch_bounds__(NT) k_add(AddParams p) {
     }
     __syncthreads();
   }
-  if (finish_arrive(&p.s.ctrl[C_DONE], &s_flag)) publish(p.s, p.res, ld_dev(&p.s.acc[A_OUT]), 0.0);
+  if (finish_arrive(&p.s.ctrl[C_DONE], &s_flag)) {
+    retire_epoch(p.s, epoch);
+    publish(p.s, p.res, ld_dev(&p.s.acc[A_OUT]), 0.0);
+  }
 }
 
 struct MulParams {
@@ -1921,7 +1945,6 @@ struct MulParams {
   uint64_t out_cap;
   MulScalar k;
   Scratch s;
-  uint32_t epoch;
   hoszp_result* res;
 };
 
@@ -1981,6 +2004,7 @@ __global__ void __launch_bounds__(NT) k_mul(MulParams p) {
   const uint32_t* S = reinterpret_cast<const uint32_t*>(p.c + g.off_s);
   const int32_t* O = reinterpret_cast<const int32_t*>(p.c + g.off_o);
   uint32_t next = 0;
+  const uint32_t epoch = launch_epoch(p.s);
   if (tid == 0) next = atomicAdd(&p.s.ctrl[C_TICKET], 1u);
   for (;;) {
     if (tid == 0) s_ticket = next;
@@ -2077,7 +2101,7 @@ __global__ void __launch_bounds__(NT) k_mul(MulParams p) {
     uint32_t tw_z;
     const uint32_t off_z = wg_scan<NT>(wz, tw_z, s_tmp);
     // publish the output tile's size, then pack and store what needs no offset
-    lb_publish(p.s.st_out, tile, tw_z, p.epoch);
+    lb_publish(p.s.st_out, tile, tw_z, epoch);
     if (wz > 0) pack32(&s_pay[off_z], mag, wz);
     if (active) {
       if (sub == 0) {
@@ -2086,7 +2110,7 @@ __global__ void __launch_bounds__(NT) k_mul(MulParams p) {
       }
       reinterpret_cast<uint32_t*>(p.out + g.off_s)[seg] = bswap32(sgn);
     }
-    const uint64_t base_z = lb_wait<NT>(p.s.st_out, tile, tw_z, p.epoch, s_lb);
+    const uint64_t base_z = lb_wait<NT>(p.s.st_out, tile, tw_z, epoch, s_lb);
     if (tid == 0) next = atomicAdd(&p.s.ctrl[C_TICKET], 1u);
     __syncthreads();
     uint32_t* Pz = reinterpret_cast<uint32_t*>(p.out + g.off_p) + base_z;
@@ -2098,7 +2122,10 @@ __global__ void __launch_bounds__(NT) k_mul(MulParams p) {
     }
     __syncthreads();
   }
-  if (finish_arrive(&p.s.ctrl[C_DONE], &s_flag)) publish(p.s, p.res, ld_dev(&p.s.acc[A_OUT]), 0.0);
+  if (finish_arrive(&p.s.ctrl[C_DONE], &s_flag)) {
+    retire_epoch(p.s, epoch);
+    publish(p.s, p.res, ld_dev(&p.s.acc[A_OUT]), 0.0);
+  }
 }
 
 // ------------------------------------------ bivariate: Hadamard, covariance
@@ -2111,7 +2138,6 @@ struct BivarParams {
   uint8_t* out;  // Hadamard only
   uint64_t out_cap;
   Scratch s;
-  uint32_t epoch;
   hoszp_result* res;
 };
 
@@ -2220,6 +2246,7 @@ __global__ void __launch_bounds__(NT) k_bivar(BivarParams p) {
   int64_t acc_a = 0, acc_b = 0;
   uint64_t acc_pl = 0, acc_ph = 0;  // 128-bit two's complement sum of q_A q_B
   uint32_t next = 0;
+  const uint32_t epoch = launch_epoch(p.s);
   if (tid == 0) next = atomicAdd(&p.s.ctrl[C_TICKET], 1u);
   for (;;) {
     if (tid == 0) s_ticket = next;
@@ -2345,7 +2372,7 @@ __global__ void __launch_bounds__(NT) k_bivar(BivarParams p) {
     const uint32_t wz = bitlen32(mx);
     uint32_t tw_z;
     const uint32_t off_z = wg_scan<NT>(wz, tw_z, s_tmp);  // barriers: all threads done reading B
-    lb_publish(p.s.st_out, tile, tw_z, p.epoch);
+    lb_publish(p.s.st_out, tile, tw_z, epoch);
     if (wz > 0) pack32(&s_pay[off_z], mag, wz);
     if (active) {
       if (sub == 0) {
@@ -2354,7 +2381,7 @@ __global__ void __launch_bounds__(NT) k_bivar(BivarParams p) {
       }
       reinterpret_cast<uint32_t*>(p.out + g.off_s)[seg] = bswap32(sgn);
     }
-    const uint64_t base_z = lb_wait<NT>(p.s.st_out, tile, tw_z, p.epoch, s_lb);
+    const uint64_t base_z = lb_wait<NT>(p.s.st_out, tile, tw_z, epoch, s_lb);
     if (tid == 0) next = atomicAdd(&p.s.ctrl[C_TICKET], 1u);
     __syncthreads();
     uint32_t* Pz = reinterpret_cast<uint32_t*>(p.out + g.off_p) + base_z;
@@ -2397,7 +2424,10 @@ __global__ void __launch_bounds__(NT) k_bivar(BivarParams p) {
     publish(p.s, p.res, 0, value);
     return;
   }
-  if (finish_arrive(&p.s.ctrl[C_DONE], &s_flag)) publish(p.s, p.res, ld_dev(&p.s.acc[A_OUT]), 0.0);
+  if (finish_arrive(&p.s.ctrl[C_DONE], &s_flag)) {
+    retire_epoch(p.s, epoch);
+    publish(p.s, p.res, ld_dev(&p.s.acc[A_OUT]), 0.0);
+  }
 }
 
 // ---------------------------------------------------- float32 workflow ops
@@ -2498,9 +2528,8 @@ static hipError_t launch_widths(const Scratch& s, const Grids& gr, int which, co
 }
 
 hipError_t launch_compress(const Scratch& s, const Grids& gr, const float* x, const Layout& g,
-                           double inv2e, uint8_t* out, uint32_t epoch, hoszp_result* res,
-                           hipStream_t st) {
-  CompressParams p{x, out, g, g.eb, inv2e, s, epoch, res};
+                           double inv2e, uint8_t* out, hoszp_result* res, hipStream_t st) {
+  CompressParams p{x, out, g, g.eb, inv2e, s, res};
   const uint64_t ntiles = (g.nseg + kCompressThreads - 1) / kCompressThreads;
   const uint64_t grid = ntiles < uint64_t(gr.compress) ? ntiles : uint64_t(gr.compress);
   switch (g.L) {
@@ -2514,9 +2543,8 @@ hipError_t launch_compress(const Scratch& s, const Grids& gr, const float* x, co
 }
 
 hipError_t launch_decompress(const Scratch& s, const Grids& gr, const uint8_t* c,
-                             uint64_t c_bytes, float* x, uint64_t n_cap, uint32_t epoch,
-                             hoszp_result* res, hipStream_t st) {
-  (void)epoch;
+                             uint64_t c_bytes, float* x, uint64_t n_cap, hoszp_result* res,
+                             hipStream_t st) {
   hipError_t e = launch_widths(s, gr, 0, c, c_bytes, st);
   if (e != hipSuccess) return e;
   DecodeParams p{c, c_bytes, x, n_cap, s, res};
@@ -2525,8 +2553,7 @@ hipError_t launch_decompress(const Scratch& s, const Grids& gr, const uint8_t* c
 }
 
 hipError_t launch_reduce(const Scratch& s, const Grids& gr, const uint8_t* c, uint64_t c_bytes,
-                         bool variance, uint32_t epoch, hoszp_result* res, hipStream_t st) {
-  (void)epoch;
+                         bool variance, hoszp_result* res, hipStream_t st) {
   hipError_t e = launch_widths(s, gr, 0, c, c_bytes, st);
   if (e != hipSuccess) return e;
   DecodeParams p{c, c_bytes, nullptr, 0, s, res};
@@ -2566,11 +2593,11 @@ hipError_t launch_shift(const Scratch& s, const Grids& gr, const uint8_t* c, uin
 
 hipError_t launch_add(const Scratch& s, const Grids& gr, const uint8_t* a, uint64_t a_bytes,
                       const uint8_t* b, uint64_t b_bytes, uint8_t* out, uint64_t out_cap,
-                      uint32_t epoch, hoszp_result* res, hipStream_t st, bool sub) {
+                      hoszp_result* res, hipStream_t st, bool sub) {
   hipError_t e = launch_widths(s, gr, 0, a, a_bytes, st);
   if (e == hipSuccess) e = launch_widths(s, gr, 1, b, b_bytes, st);
   if (e != hipSuccess) return e;
-  AddParams p{a, a_bytes, b, b_bytes, out, out_cap, s, epoch, res};
+  AddParams p{a, a_bytes, b, b_bytes, out, out_cap, s, res};
   if (sub)
     hipLaunchKernelGGL((k_add<kAddThreads, true>), dim3(gr.add), dim3(kAddThreads), 0, st, p);
   else
@@ -2579,22 +2606,22 @@ hipError_t launch_add(const Scratch& s, const Grids& gr, const uint8_t* a, uint6
 }
 
 hipError_t launch_mul(const Scratch& s, const Grids& gr, const uint8_t* c, uint64_t c_bytes,
-                      MulScalar k, uint8_t* out, uint64_t out_cap, uint32_t epoch,
-                      hoszp_result* res, hipStream_t st) {
+                      MulScalar k, uint8_t* out, uint64_t out_cap, hoszp_result* res,
+                      hipStream_t st) {
   hipError_t e = launch_widths(s, gr, 0, c, c_bytes, st);
   if (e != hipSuccess) return e;
-  MulParams p{c, c_bytes, out, out_cap, k, s, epoch, res};
+  MulParams p{c, c_bytes, out, out_cap, k, s, res};
   hipLaunchKernelGGL(k_mul<kMulThreads>, dim3(gr.mul), dim3(kMulThreads), 0, st, p);
   return hipGetLastError();
 }
 
 hipError_t launch_bivar(const Scratch& s, const Grids& gr, bool covariance, const uint8_t* a,
                         uint64_t a_bytes, const uint8_t* b, uint64_t b_bytes, uint8_t* out,
-                        uint64_t out_cap, uint32_t epoch, hoszp_result* res, hipStream_t st) {
+                        uint64_t out_cap, hoszp_result* res, hipStream_t st) {
   hipError_t e = launch_widths(s, gr, 0, a, a_bytes, st);
   if (e == hipSuccess) e = launch_widths(s, gr, 1, b, b_bytes, st);
   if (e != hipSuccess) return e;
-  BivarParams p{a, a_bytes, b, b_bytes, out, out_cap, s, epoch, res};
+  BivarParams p{a, a_bytes, b, b_bytes, out, out_cap, s, res};
   if (covariance)
     hipLaunchKernelGGL((k_bivar<kCovariance, kBivarThreads>), dim3(gr.bivar), dim3(kBivarThreads), 0, st, p);
   else

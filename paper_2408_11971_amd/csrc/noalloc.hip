@@ -100,13 +100,12 @@ extern "C" int hoszp_compress_noalloc(const float* d_x, uint64_t n, double eb, u
   // array keeps the previous call's contents), cleared by a kernel on the
   // caller's stream: no memset node, and a captured graph clears them again
   // on every replay, so the look-back never sees a previous call's prefixes
-  // and one generation (1) suffices.
+  // (the kernel's generation counter restarts at 1 with them).
   const uint64_t tiles = (g.nseg + 1023) / 1024;
   hipLaunchKernelGGL(k_noalloc_clear, dim3(8), dim3(256), 0, st, d.ptr, kCtrlWords + tiles);
   if (hipGetLastError() != hipSuccess) return HOSZP_ERR_DEVICE;
-  const uint32_t e = 1;
   const double inv2e = 1.0 / (2.0 * eb);
-  if (hz::launch_compress(s, d.grids, d_x, g, inv2e, static_cast<uint8_t*>(d_out), e, d_res, st) !=
+  if (hz::launch_compress(s, d.grids, d_x, g, inv2e, static_cast<uint8_t*>(d_out), d_res, st) !=
       hipSuccess) {
     (void)hipGetLastError();
     (void)hz::launch_reset(s, d_res, st);
