@@ -9,15 +9,20 @@ stream):
     compress A, compress B, mean(A), decompress(B), variance(A), negate(B),
     add(A, B), mul(A, 3.14)
 
-The ops are ordered so consecutive ops read different streams (the 256 MB
-last-level cache is refilled by the large float32 traffic in between).  One
-instrumented step before the timed ones names the kernel with the largest
-share of a step; the timed steps carry HIP events only around that kernel's
-launches (the roofline's live durations).  The per-op table comes from
-instrumented steps after them.  Then the decompress-then-compute workflow
-(decompress, float32 op in HBM, re-compress for compression-as-output ops) is
-timed the same way for the comparison, and the CPU oracle is timed on a
-bounded sample.
+Every op of a step reads its own copy of its input streams (four copies of
+each stream per bound, made once), so no op finds its input in the 256 MB
+last-level cache because the op before it just read it.  One instrumented
+step before the timed ones names the kernel with the largest share of a
+step; the timed steps carry HIP events only around that kernel's launches
+(the roofline's live durations).  The per-op table times every op alone
+after a 1 GiB cache-flushing write (median of --reps), the step's ops and
+the remaining Table II ops (element-wise subtraction, scalar addition,
+Hadamard product, covariance, block means); the decompress-then-compute
+workflow (decompress, float32 op in HBM, re-compress for
+compression-as-output ops) is timed the same way for the comparison.  Then
+the climate-like sweep (100 1800x3600 steps, blocks 32/64/128; each op over
+the whole sweep, captured in a graph and replayed), and the CPU oracle on a
+bounded sample, on one thread and on all host cores.
 
 stdout: one JSON line.  Diagnostics go to stderr.
 """
@@ -49,7 +54,12 @@ def parse():
     ap.add_argument("--n", type=int, default=512, help="edge of the cubic field")
     ap.add_argument("--cpu-sample", type=int, default=1 << 24,
                     help="elements of each field the oracle is timed on (0 = skip)")
+    ap.add_argument("--reps", type=int, default=5, help="flushed repetitions per op")
     ap.add_argument("--trad-reps", type=int, default=3)
+    ap.add_argument("--climate-steps", type=int, default=100,
+                    help="climate-like 1800x3600 steps of the sweep leg (0 = skip)")
+    ap.add_argument("--cpu-threads", type=int, default=16,
+                    help="most host threads for the all-core oracle leg")
     ap.add_argument("--workload", choices=("grf512", "batch", "serve"), default="grf512",
                     help="grf512: the 512^3 field ops (default); batch: 4096 uneven fields "
                          "compressed with mean/variance in one captured launch; serve: Poisson "
@@ -89,6 +99,38 @@ class Timer:
         return 1000.0 * sum(s.elapsed_time(e) for s, e in ps) / len(ps)
 
 
+FLUSH_BYTES = 1 << 30
+COPIES = 4  # read-only copies of each stream per bound: every op of a step reads its own
+
+
+class Flusher:
+    """Writes a 1 GiB buffer, which evicts the L2 caches and the 256 MB
+    last-level cache, so the op timed next reads its inputs from HBM."""
+
+    def __init__(self, torch, dev):
+        self.buf = torch.empty(FLUSH_BYTES // 4, dtype=torch.float32, device=dev)
+
+    def __call__(self):
+        self.buf.fill_(1.0)
+
+
+def time_flushed(torch, flush, fn, reps):
+    """Median device time (us) of fn over `reps` runs, each after a flush,
+    with HIP events on the current stream around fn alone."""
+    pairs = []
+    for _ in range(reps):
+        flush()
+        s = torch.cuda.Event(enable_timing=True)
+        e = torch.cuda.Event(enable_timing=True)
+        s.record()
+        fn()
+        e.record()
+        pairs.append((s, e))
+    torch.cuda.synchronize()
+    ts = sorted(1000.0 * s.elapsed_time(e) for s, e in pairs)
+    return ts[len(ts) // 2]
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -99,7 +141,6 @@ def main():
         return bench_batch(args)
     if args.workload == "serve":
         return bench_serve(args)
-    import numpy as np
     import torch
 
     import paper_2408_11971_amd as hz
@@ -116,33 +157,46 @@ def main():
     rng = synth.value_range(A)
     ebs = [rel * rng for rel in RELS]
     cap = hz.compress_bound(N, BLOCK)
-    bufs = {}
-    for i, _ in enumerate(ebs):
-        for k in ("a", "b", "neg", "sum", "mul", "trad"):
-            bufs[(i, k)] = torch.empty(cap, dtype=torch.uint8, device=dev)
+    W = [{k: torch.empty(cap, dtype=torch.uint8, device=dev)
+          for k in ("a", "b", "neg", "sum", "mul", "sub", "sadd", "had", "trad")} for _ in ebs]
     dec = torch.empty(N, dtype=torch.float32, device=dev)
     d2 = torch.empty(N, dtype=torch.float32, device=dev)
     t32 = torch.empty(N, dtype=torch.float32, device=dev)
+    nbk = (N + BLOCK - 1) // BLOCK
+    bmeans = torch.empty(nbk, dtype=torch.float64, device=dev)
     res = {name: hz.new_result(dev) for name in
-           ("ca", "cb", "mean", "dec", "var", "neg", "add", "mul", "t0", "t1", "t2")}
-
-    def step(tm):
-        for i, eb in enumerate(ebs):
-            ca, cb = bufs[(i, "a")], bufs[(i, "b")]
-            tm.run((i, "compress"), lambda: hz.compress_async(A, eb, BLOCK, ca, res["ca"], ctx))
-            tm.run((i, "compress_b"), lambda: hz.compress_async(B, eb, BLOCK, cb, res["cb"], ctx))
-            tm.run((i, "mean"), lambda: hz.mean_async(ca, res["mean"], ctx))
-            tm.run((i, "decompress"), lambda: hz.decompress_async(cb, dec, res["dec"], ctx))
-            tm.run((i, "variance"), lambda: hz.variance_async(ca, res["var"], ctx))
-            tm.run((i, "negate"), lambda: hz.negate_async(cb, bufs[(i, "neg")], res["neg"], ctx))
-            tm.run((i, "add"), lambda: hz.add_async(ca, cb, bufs[(i, "sum")], res["add"], ctx))
-            tm.run((i, "mul"), lambda: hz.mul_async(ca, SCALAR, bufs[(i, "mul")], res["mul"], ctx))
+           ("ca", "cb", "mean", "dec", "var", "neg", "add", "mul", "sub", "sadd", "had", "cov",
+            "bm", "t0", "t1", "t2")}
 
     def check(name):
         r = hz.read_result(res[name], ctx)
         if r["code"] != 0:
             raise RuntimeError(f"{name} failed with code {r['code']}")
         return r
+
+    # the streams of every bound, and COPIES read-only copies of each: the ops
+    # of a step read different copies, so no op finds its input in a cache
+    # because the op before it touched it (a copy is read once per step)
+    R = []
+    for i, eb in enumerate(ebs):
+        hz.compress_async(A, eb, BLOCK, W[i]["a"], res["ca"], ctx)
+        hz.compress_async(B, eb, BLOCK, W[i]["b"], res["cb"], ctx)
+        ca_b, cb_b = check("ca")["out_bytes"], check("cb")["out_bytes"]
+        R.append(([W[i]["a"][:ca_b].clone() for _ in range(COPIES)],
+                  [W[i]["b"][:cb_b].clone() for _ in range(COPIES)]))
+
+    def step(tm):
+        for i, eb in enumerate(ebs):
+            RA, RB = R[i]
+            w = W[i]
+            tm.run((i, "compress"), lambda: hz.compress_async(A, eb, BLOCK, w["a"], res["ca"], ctx))
+            tm.run((i, "compress_b"), lambda: hz.compress_async(B, eb, BLOCK, w["b"], res["cb"], ctx))
+            tm.run((i, "mean"), lambda: hz.mean_async(RA[0], res["mean"], ctx))
+            tm.run((i, "decompress"), lambda: hz.decompress_async(RB[0], dec, res["dec"], ctx))
+            tm.run((i, "variance"), lambda: hz.variance_async(RA[1], res["var"], ctx))
+            tm.run((i, "negate"), lambda: hz.negate_async(RB[1], w["neg"], res["neg"], ctx))
+            tm.run((i, "add"), lambda: hz.add_async(RA[2], RB[2], w["sum"], res["add"], ctx))
+            tm.run((i, "mul"), lambda: hz.mul_async(RA[3], SCALAR, w["mul"], res["mul"], ctx))
 
     log("warmup")
     for _ in range(args.warmup):
@@ -154,8 +208,7 @@ def main():
     # One instrumented, untimed step names the kernel with the largest share
     # of a step; the timed steps carry HIP events only around that kernel's
     # launches (its live duration is the roofline's denominator), so event
-    # packets between the other ops do not slow the steps being timed.  The
-    # per-op table comes from instrumented steps after the timed ones.
+    # packets between the other ops do not slow the steps being timed.
     probe = Timer(torch)
     step(probe)
     torch.cuda.synchronize()
@@ -174,30 +227,28 @@ def main():
     ms_per_step = 1000.0 * wall / args.steps
     for name in ("ca", "cb", "mean", "dec", "var", "neg", "add", "mul"):
         check(name)
-    ti = Timer(torch)
-    for _ in range(max(3, min(args.steps, 10))):
-        step(ti)
-    torch.cuda.synchronize()
 
-    # sizes of the streams of every bound (from the last step's result records)
+    # output sizes and block statistics of every bound
     sizes = []
     for i, eb in enumerate(ebs):
-        hz.compress_async(A, eb, BLOCK, bufs[(i, "a")], res["ca"], ctx)
-        hz.compress_async(B, eb, BLOCK, bufs[(i, "b")], res["cb"], ctx)
-        ca_b = check("ca")["out_bytes"]
-        cb_b = check("cb")["out_bytes"]
-        hz.add_async(bufs[(i, "a")], bufs[(i, "b")], bufs[(i, "sum")], res["add"], ctx)
-        hz.negate_async(bufs[(i, "b")], bufs[(i, "neg")], res["neg"], ctx)
-        hz.mul_async(bufs[(i, "a")], SCALAR, bufs[(i, "mul")], res["mul"], ctx)
-        cz_b = check("add")["out_bytes"]
-        cn_b = check("neg")["out_bytes"]
-        cm_b = check("mul")["out_bytes"]
-        h = hz.header_of(bufs[(i, "a")])
-        nb = h["nb"]
-        w = bufs[(i, "a")][64:64 + nb].to(torch.int32)
-        nonconst = int((w > 0).sum().item())
-        sizes.append({"ca": ca_b, "cb": cb_b, "sum": cz_b, "neg": cn_b, "mul": cm_b, "nb": nb,
-                      "nonconst": nonconst, "payload": h["payload_bytes"]})
+        RA, RB = R[i]
+        w = W[i]
+        hz.add_async(RA[2], RB[2], w["sum"], res["add"], ctx)
+        hz.negate_async(RB[1], w["neg"], res["neg"], ctx)
+        hz.mul_async(RA[3], SCALAR, w["mul"], res["mul"], ctx)
+        hz.sub_async(RA[0], RB[0], w["sub"], res["sub"], ctx)
+        hz.scalar_add_async(RB[1], SCALAR, w["sadd"], res["sadd"], ctx)
+        hz.hadamard_async(RA[2], RB[2], w["had"], res["had"], ctx)
+        sz = {k: check(r)["out_bytes"] for k, r in (("sum", "add"), ("neg", "neg"), ("mul", "mul"),
+                                                   ("sub", "sub"), ("sadd", "sadd"), ("had", "had"))}
+        sz["ca"], sz["cb"] = RA[0].numel(), RB[0].numel()
+        for key, c in (("a", RA[0]), ("b", RB[0])):
+            h = hz.header_of(c)
+            wd = c[64:64 + h["nb"]].to(torch.int32)
+            sz["nonconst_" + key] = int((wd > 0).sum().item())
+            sz["payload_" + key] = h["payload_bytes"]
+        sz["nb"] = nbk
+        sizes.append(sz)
 
     # ---- plain device copy of one field: the measured HBM ceiling (read + write 4N bytes)
     tc = Timer(torch)
@@ -206,77 +257,90 @@ def main():
     torch.cuda.synchronize()
     copy_gbps = 8 * N / tc.mean_us("copy") / 1e3
 
-    # ---- decompress-then-compute workflow
-    log("timing the decompress-then-compute workflow")
-    tt = Timer(torch)
-    for _ in range(args.trad_reps):
-        for i, eb in enumerate(ebs):
-            ca, cb, ct = bufs[(i, "a")], bufs[(i, "b")], bufs[(i, "trad")]
-
-            def t_mean():
-                hz.decompress_async(ca, dec, res["t0"], ctx)
-                hz.f32_mean_async(dec, res["t1"], ctx)
-
-            def t_var():
-                hz.decompress_async(ca, dec, res["t0"], ctx)
-                hz.f32_variance_async(dec, res["t1"], ctx)
-
-            def t_add():
-                hz.decompress_async(ca, dec, res["t0"], ctx)
-                hz.decompress_async(cb, d2, res["t1"], ctx)
-                hz.f32_add_async(dec, d2, t32, ctx)
-                hz.compress_async(t32, eb, BLOCK, ct, res["t2"], ctx)
-
-            def t_neg():
-                hz.decompress_async(cb, dec, res["t0"], ctx)
-                hz.f32_negate_async(dec, t32, ctx)
-                hz.compress_async(t32, eb, BLOCK, ct, res["t2"], ctx)
-
-            def t_mul():
-                hz.decompress_async(ca, dec, res["t0"], ctx)
-                hz.f32_mul_async(dec, SCALAR, t32, ctx)
-                hz.compress_async(t32, eb, BLOCK, ct, res["t2"], ctx)
-
-            for key, fn in (("mean", t_mean), ("variance", t_var), ("add", t_add),
-                            ("negate", t_neg), ("mul", t_mul)):
-                tt.run((i, key), fn)
-    torch.cuda.synchronize()
-    for name in ("t0", "t1", "t2"):
-        check(name)
-
-    # ---- per-op figures
+    # ---- every op alone, after a cache flush, and the decompress-then-compute
+    # workflow the same way
+    log("timing each op after a cache flush, homomorphic and decompress-then-compute")
+    flush = Flusher(torch, dev)
     ops = {}
     raw_per_step = 0
     launches = []  # (algorithmic bytes, us, rel, op) of the dominant kernel's launches in a step
     for i, rel in enumerate(RELS):
+        RA, RB = R[i]
+        w = W[i]
+        eb = ebs[i]
         sz = sizes[i]
         C, Cb = sz["ca"], sz["cb"]
-        red_bytes = sz["nb"] + 4 * sz["nb"] + 4 * sz["nonconst"] + sz["payload"]
-        table = {
-            "compress": (4 * N, 4 * N + C, ti.mean_us((i, "compress"))),
-            "decompress": (4 * N, Cb + 4 * N, ti.mean_us((i, "decompress"))),
-            "mean": (4 * N, red_bytes, ti.mean_us((i, "mean"))),
-            "variance": (4 * N, red_bytes, ti.mean_us((i, "variance"))),
-            "negate": (4 * N, 2 * Cb, ti.mean_us((i, "negate"))),
-            "add": (8 * N, C + Cb + sz["sum"], ti.mean_us((i, "add"))),
-            "mul": (4 * N, C + sz["mul"], ti.mean_us((i, "mul"))),
+        red_a = sz["nb"] + 4 * sz["nb"] + 4 * sz["nonconst_a"] + sz["payload_a"]
+        red_b = sz["nb"] + 4 * sz["nb"] + 4 * sz["nonconst_b"] + sz["payload_b"]
+        hom = {
+            "compress": (4 * N, 4 * N + C,
+                         lambda: hz.compress_async(A, eb, BLOCK, w["a"], res["ca"], ctx)),
+            "decompress": (4 * N, Cb + 4 * N,
+                           lambda: hz.decompress_async(RB[0], dec, res["dec"], ctx)),
+            "mean": (4 * N, red_a, lambda: hz.mean_async(RA[0], res["mean"], ctx)),
+            "variance": (4 * N, red_a, lambda: hz.variance_async(RA[1], res["var"], ctx)),
+            "negate": (4 * N, 2 * Cb, lambda: hz.negate_async(RB[1], w["neg"], res["neg"], ctx)),
+            "add": (8 * N, C + Cb + sz["sum"],
+                    lambda: hz.add_async(RA[2], RB[2], w["sum"], res["add"], ctx)),
+            "mul": (4 * N, C + sz["mul"],
+                    lambda: hz.mul_async(RA[3], SCALAR, w["mul"], res["mul"], ctx)),
+            "sub": (8 * N, C + Cb + sz["sub"],
+                    lambda: hz.sub_async(RA[0], RB[0], w["sub"], res["sub"], ctx)),
+            "scalar_add": (4 * N, 2 * Cb,
+                           lambda: hz.scalar_add_async(RB[1], SCALAR, w["sadd"], res["sadd"], ctx)),
+            "hadamard": (8 * N, C + Cb + sz["had"],
+                         lambda: hz.hadamard_async(RA[2], RB[2], w["had"], res["had"], ctx)),
+            "covariance": (8 * N, red_a + red_b,
+                           lambda: hz.covariance_async(RA[3], RB[3], res["cov"], ctx)),
+            "block_means": (4 * N, red_a + 8 * sz["nb"],
+                            lambda: hz.block_means_async(RA[0], bmeans, res["bm"], ctx)),
         }
-        raw_per_step += sum(v[0] for v in table.values()) + 4 * N  # + compress of B
-        row = {"cr": round(4 * N / C, 3), "const_block_pct": round(100.0 * (1 - sz["nonconst"] / sz["nb"]), 2)}
-        for op, (raw, alg, us) in table.items():
+
+        def dec1(c):
+            hz.decompress_async(c, dec, res["t0"], ctx)
+
+        def dec2(a, b):
+            hz.decompress_async(a, dec, res["t0"], ctx)
+            hz.decompress_async(b, d2, res["t1"], ctx)
+
+        def recompress():
+            hz.compress_async(t32, eb, BLOCK, w["trad"], res["t2"], ctx)
+
+        trad = {
+            "mean": lambda: (dec1(RA[0]), hz.f32_mean_async(dec, res["t1"], ctx)),
+            "variance": lambda: (dec1(RA[1]), hz.f32_variance_async(dec, res["t1"], ctx)),
+            "negate": lambda: (dec1(RB[1]), hz.f32_negate_async(dec, t32, ctx), recompress()),
+            "add": lambda: (dec2(RA[2], RB[2]), hz.f32_add_async(dec, d2, t32, ctx), recompress()),
+            "mul": lambda: (dec1(RA[3]), hz.f32_mul_async(dec, SCALAR, t32, ctx), recompress()),
+            "sub": lambda: (dec2(RA[0], RB[0]), hz.f32_sub_async(dec, d2, t32, ctx), recompress()),
+            "scalar_add": lambda: (dec1(RB[1]), hz.f32_scalar_add_async(dec, SCALAR, t32, ctx),
+                                   recompress()),
+            "hadamard": lambda: (dec2(RA[2], RB[2]), hz.f32_hadamard_async(dec, d2, t32, ctx),
+                                 recompress()),
+        }
+        row = {"cr": round(4 * N / C, 3),
+               "const_block_pct": round(100.0 * (1 - sz["nonconst_a"] / sz["nb"]), 2)}
+        for op, (raw, alg, fn) in hom.items():
+            us = time_flushed(torch, flush, fn, args.reps)
             entry = {"us": round(us, 2), "gbps_raw": round(raw / us / 1e3, 1),
                      "hbm_gbps": round(alg / us / 1e3, 1),
                      "hbm_frac": round(alg / us / 1e3 / HBM_PEAK_GBS, 4)}
-            if op in ("mean", "variance", "negate", "add", "mul"):
-                trad = tt.mean_us((i, op))
-                entry["trad_us"] = round(trad, 2)
-                entry["speedup_vs_trad"] = round(trad / us, 2)
+            if op in trad:
+                t_us = time_flushed(torch, flush, trad[op], args.trad_reps)
+                entry["trad_us"] = round(t_us, 2)
+                entry["speedup_vs_trad"] = round(t_us / us, 2)
             row[op] = entry
+            if op in KERNEL_OF:
+                raw_per_step += raw
             if op in timed_ops:  # the dominant kernel: durations from the timed steps
                 launches.append((alg, tm.mean_us((i, op)), rel, op))
+        raw_per_step += 4 * N  # compress of B
         if "compress_b" in timed_ops:
             launches.append((4 * N + Cb, tm.mean_us((i, "compress_b")), rel, "compress_b"))
         ops[f"rel{rel:g}"] = row
+    for name in ("ca", "dec", "mean", "var", "neg", "add", "mul", "sub", "sadd", "had", "cov",
+                 "bm", "t0", "t1", "t2"):
+        check(name)
 
     value = raw_per_step / (ms_per_step / 1000.0) / 1e9
     ls = launches
@@ -290,9 +354,17 @@ def main():
                 "bytes_per_launch": round(alg_avg), "us_per_launch": round(us_avg, 2),
                 "events_include": PREPASS_NOTE.get(kname, "the kernel alone")}
 
+    climate = None
+    if args.climate_steps > 0:
+        del dec, d2, t32, bmeans
+        R.clear()
+        W.clear()
+        torch.cuda.empty_cache()
+        climate = bench_climate(args, torch, hz, synth, ctx, dev)
+
     cpu = None
     if args.cpu_sample > 0:
-        cpu = cpu_baseline(A, B, ebs, min(args.cpu_sample, N))
+        cpu = cpu_baseline(A, B, ebs, min(args.cpu_sample, N), args.cpu_threads)
 
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1,
@@ -302,12 +374,128 @@ def main():
         "config": {"workload": f"grf3d_{n3}^3_k-5/3_two_fields", "n": N, "block": BLOCK,
                    "rel_eb": list(RELS), "ops_per_step": 8 * len(RELS),
                    "raw_bytes_per_step": raw_per_step, "parallelism": "single_gpu",
-                   "copy_gbps": round(copy_gbps, 1)},
+                   "copy_gbps": round(copy_gbps, 1),
+                   "step_reads": f"each op of a step reads its own one of {COPIES} copies of "
+                                 "its input streams (a copy is read once per step)",
+                   "ops_timing": f"each op alone after a {FLUSH_BYTES >> 20} MiB cache-flushing "
+                                 f"write, median of {args.reps} (decompress-then-compute: "
+                                 f"{args.trad_reps})"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "ops": ops,
+        "climate": climate,
     }
     print(json.dumps(line), flush=True)
+
+
+def graph_us(torch, body, reps):
+    """Capture body() (async library calls on the current stream) in a graph,
+    replay it `reps` times and return the median replay time (us)."""
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        body()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        body()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        g.replay()
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(1000.0 * a.elapsed_time(b))
+    del g
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def bench_climate(args, torch, hz, synth, ctx, dev):
+    """The climate-like sweep: `climate_steps` 1800x3600 float32 steps made on
+    the GPU, one error bound for the whole sweep (1e-4 of its value range, so
+    consecutive steps can be added), blocks 32/64/128.  Each op runs over the
+    whole sweep (per-step mean/variance/negate/scalar multiply, pairwise
+    add of steps t and t+1), captured in a graph and replayed (median of 3);
+    decompress-then-compute the same way."""
+    import numpy as np
+
+    T = args.climate_steps
+    log(f"generating {T} climate-like 1800x3600 steps on the GPU")
+    X = synth.climate_steps_device(T, device=dev)
+    n = X.shape[1]
+    eb = 1e-4 * synth.value_range(X)
+    scal = np.random.default_rng(9).uniform(-2.0, 2.0, T).tolist()
+    res = [hz.new_result(dev) for _ in range(3)]
+    dec = torch.empty(n, dtype=torch.float32, device=dev)
+    d2 = torch.empty(n, dtype=torch.float32, device=dev)
+    t32 = torch.empty(n, dtype=torch.float32, device=dev)
+    out = {"steps": T, "shape": [1800, 3600], "eb": eb, "blocks": {}}
+    for L in (32, 64, 128):
+        log(f"climate sweep, block {L}")
+        cap = hz.compress_bound(n, L)
+        C = [torch.empty(cap, dtype=torch.uint8, device=dev) for _ in range(T)]
+        o = torch.empty(cap, dtype=torch.uint8, device=dev)
+        sizes = []
+        for t in range(T):
+            hz.compress_async(X[t], eb, L, C[t], res[0], ctx)
+            r = hz.read_result(res[0], ctx)
+            if r["code"] != 0:
+                raise RuntimeError(f"climate compress failed: {r['code']}")
+            sizes.append(r["out_bytes"])
+        S = [C[t][:sizes[t]] for t in range(T)]
+        hom = {
+            "compress": (4 * n * T, lambda: [hz.compress_async(X[t], eb, L, C[t], res[0], ctx)
+                                             for t in range(T)]),
+            "decompress": (4 * n * T, lambda: [hz.decompress_async(S[t], dec, res[0], ctx)
+                                               for t in range(T)]),
+            "mean": (4 * n * T, lambda: [hz.mean_async(S[t], res[0], ctx) for t in range(T)]),
+            "variance": (4 * n * T, lambda: [hz.variance_async(S[t], res[0], ctx)
+                                             for t in range(T)]),
+            "negate": (4 * n * T, lambda: [hz.negate_async(S[t], o, res[0], ctx) for t in range(T)]),
+            "add": (8 * n * (T - 1), lambda: [hz.add_async(S[t], S[t + 1], o, res[0], ctx)
+                                              for t in range(T - 1)]),
+            "mul": (4 * n * T, lambda: [hz.mul_async(S[t], scal[t], o, res[0], ctx)
+                                        for t in range(T)]),
+        }
+
+        def trad_unary(t, f32op):
+            hz.decompress_async(S[t], dec, res[1], ctx)
+            f32op(t)
+
+        trad = {
+            "mean": lambda: [trad_unary(t, lambda t: hz.f32_mean_async(dec, res[2], ctx))
+                             for t in range(T)],
+            "variance": lambda: [trad_unary(t, lambda t: hz.f32_variance_async(dec, res[2], ctx))
+                                 for t in range(T)],
+            "negate": lambda: [(trad_unary(t, lambda t: hz.f32_negate_async(dec, t32, ctx)),
+                                hz.compress_async(t32, eb, L, o, res[2], ctx)) for t in range(T)],
+            "add": lambda: [(hz.decompress_async(S[t], dec, res[1], ctx),
+                             hz.decompress_async(S[t + 1], d2, res[1], ctx),
+                             hz.f32_add_async(dec, d2, t32, ctx),
+                             hz.compress_async(t32, eb, L, o, res[2], ctx)) for t in range(T - 1)],
+            "mul": lambda: [(trad_unary(t, lambda t: hz.f32_mul_async(dec, scal[t], t32, ctx)),
+                             hz.compress_async(t32, eb, L, o, res[2], ctx)) for t in range(T)],
+        }
+        row = {"cr": round(4 * n * T / sum(sizes), 3)}
+        for op, (raw, body) in hom.items():
+            us = graph_us(torch, body, 3)
+            entry = {"us_per_sweep": round(us, 1), "gbps_raw": round(raw / us / 1e3, 1)}
+            if op in trad:
+                t_us = graph_us(torch, trad[op], 3)
+                entry["trad_us_per_sweep"] = round(t_us, 1)
+                entry["speedup_vs_trad"] = round(t_us / us, 2)
+            row[op] = entry
+        for r in res:
+            rr = hz.read_result(r, ctx)
+            if rr["code"] != 0:
+                raise RuntimeError(f"climate sweep failed: {rr['code']}")
+        out["blocks"][str(L)] = row
+        del C, S, o
+        torch.cuda.empty_cache()
+    return out
 
 
 def bench_batch(args):
@@ -624,17 +812,21 @@ def measured_traffic(kname, ls):
     return round(sum(vals) / len(vals))
 
 
-def cpu_baseline(A, B, ebs, n):
-    """The oracle, single-threaded, on the first n elements of both fields."""
-    import numpy as np
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
+
+def oracle_pass(a, b, ebs):
+    """The 8 ops of a step (at every bound) by the oracle on host arrays;
+    returns raw-equivalent bytes processed."""
     from oracle import ref
 
-    a = A[:n].cpu().numpy()
-    b = B[:n].cpu().numpy()
-    log(f"timing the CPU oracle on {n} elements per field")
-    raw = 0
-    t0 = time.perf_counter()
     for eb in ebs:
         ca = ref.compress(a, eb, BLOCK)
         cb = ref.compress(b, eb, BLOCK)
@@ -644,11 +836,40 @@ def cpu_baseline(A, B, ebs, n):
         ref.negate(cb)
         ref.add(ca, cb)
         ref.mul(ca, SCALAR)
-        raw += 4 * n * 9
-    sec = time.perf_counter() - t0
-    return {"value": round(raw / sec / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+    return 4 * a.size * 9 * len(ebs)
+
+
+def cpu_baseline(A, B, ebs, n, threads=None):
+    """The oracle (unchanged, single-threaded code) on the first n elements of
+    both fields: once on one thread, then on all host cores (up to
+    --cpu-threads), each thread running the same op sequence on its own
+    block-aligned slice.  The oracle is C called through ctypes, which
+    releases the interpreter lock, so the threads run in parallel."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    a = A[:n].cpu().numpy()
+    b = B[:n].cpu().numpy()
+    log(f"timing the CPU oracle on {n} elements per field, 1 thread")
+    t0 = time.perf_counter()
+    raw = oracle_pass(a, b, ebs)
+    sec1 = time.perf_counter() - t0
+    avail = len(os.sched_getaffinity(0))
+    p = max(1, min(threads or avail, avail))
+    per = (n // p + BLOCK - 1) // BLOCK * BLOCK
+    parts = [(a[k:k + per], b[k:k + per]) for k in range(0, n, per)]
+    log(f"timing the CPU oracle on {len(parts)} threads")
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=len(parts)) as ex:
+        rawp = sum(ex.map(lambda ab: oracle_pass(ab[0], ab[1], ebs), parts))
+    secp = time.perf_counter() - t0
+    return {"value": round(rawp / secp / 1e9, 4), "unit": "GB/s", "cores": len(parts),
+            "kind": "oracle",
             "sample": f"first {n} elements of each 512^3 field, the 8 ops of a step at all 3 "
-                      f"bounds ({sec:.1f} s)"}
+                      f"bounds, split into {len(parts)} block-aligned slices run on one thread "
+                      f"each ({secp:.1f} s)",
+            "one_core": {"value": round(raw / sec1 / 1e9, 4), "cores": 1,
+                         "seconds": round(sec1, 2)},
+            "host": {"nproc": os.cpu_count(), "affinity": avail, "cpu_model": cpu_model()}}
 
 
 if __name__ == "__main__":

@@ -276,14 +276,21 @@ int hoszp_std(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, double* std, void
 /* ---- decompress-then-compute path (the comparison workflow) ------------ */
 
 /* Float32 operations on decompressed fields, used to time the traditional
- * workflow (Sec. VI-B, Fig. 4a): y = -x, y = a + b, y = (float)(s * x) over n
- * elements, and the float64 mean / population variance of x.  Results of the
+ * workflow (Sec. VI-B, Fig. 4a): y = -x, y = a + b, y = (float)(s * x),
+ * y = a - b, y = (float)(x + s), y = a * b over n elements, and the float64
+ * mean / population variance of x.  Results of the
  * reductions land in d_res->value. */
 int hoszp_f32_negate_async(hoszp_ctx* ctx, const float* d_x, float* d_y, uint64_t n, void* stream);
 int hoszp_f32_add_async(hoszp_ctx* ctx, const float* d_a, const float* d_b, float* d_y,
                         uint64_t n, void* stream);
 int hoszp_f32_mul_async(hoszp_ctx* ctx, const float* d_x, double s, float* d_y, uint64_t n,
                         void* stream);
+int hoszp_f32_sub_async(hoszp_ctx* ctx, const float* d_a, const float* d_b, float* d_y,
+                        uint64_t n, void* stream);
+int hoszp_f32_scalar_add_async(hoszp_ctx* ctx, const float* d_x, double s, float* d_y,
+                               uint64_t n, void* stream);
+int hoszp_f32_hadamard_async(hoszp_ctx* ctx, const float* d_a, const float* d_b, float* d_y,
+                             uint64_t n, void* stream);
 int hoszp_f32_mean_async(hoszp_ctx* ctx, const float* d_x, uint64_t n, hoszp_result* d_res,
                          void* stream);
 int hoszp_f32_variance_async(hoszp_ctx* ctx, const float* d_x, uint64_t n, hoszp_result* d_res,

@@ -131,6 +131,9 @@ _SIGNATURES = {
     "hoszp_f32_negate_async": (_INT, [_VP, _VP, _VP, _U64, _VP]),
     "hoszp_f32_add_async": (_INT, [_VP, _VP, _VP, _VP, _U64, _VP]),
     "hoszp_f32_mul_async": (_INT, [_VP, _VP, _DBL, _VP, _U64, _VP]),
+    "hoszp_f32_sub_async": (_INT, [_VP, _VP, _VP, _VP, _U64, _VP]),
+    "hoszp_f32_scalar_add_async": (_INT, [_VP, _VP, _DBL, _VP, _U64, _VP]),
+    "hoszp_f32_hadamard_async": (_INT, [_VP, _VP, _VP, _VP, _U64, _VP]),
     "hoszp_f32_mean_async": (_INT, [_VP, _VP, _U64, _VP, _VP]),
     "hoszp_f32_variance_async": (_INT, [_VP, _VP, _U64, _VP, _VP]),
     "hoszp_result_wait": (_INT, [_VP, _VP, ctypes.POINTER(Result), _VP]),
@@ -556,6 +559,24 @@ def f32_mul_async(x, s, y, ctx=None, stream=None):
     ctx = ctx or context(x.device.index)
     _check(_lib().hoszp_f32_mul_async(ctx.handle, _ptr(x), float(s), _ptr(y), x.numel(),
                                       _stream(stream)), "f32_mul_async")
+
+
+def f32_sub_async(a, b, y, ctx=None, stream=None):
+    ctx = ctx or context(a.device.index)
+    _check(_lib().hoszp_f32_sub_async(ctx.handle, _ptr(a), _ptr(b), _ptr(y), a.numel(),
+                                      _stream(stream)), "f32_sub_async")
+
+
+def f32_scalar_add_async(x, s, y, ctx=None, stream=None):
+    ctx = ctx or context(x.device.index)
+    _check(_lib().hoszp_f32_scalar_add_async(ctx.handle, _ptr(x), float(s), _ptr(y), x.numel(),
+                                             _stream(stream)), "f32_scalar_add_async")
+
+
+def f32_hadamard_async(a, b, y, ctx=None, stream=None):
+    ctx = ctx or context(a.device.index)
+    _check(_lib().hoszp_f32_hadamard_async(ctx.handle, _ptr(a), _ptr(b), _ptr(y), a.numel(),
+                                           _stream(stream)), "f32_hadamard_async")
 
 
 def f32_mean_async(x, res, ctx=None, stream=None):

@@ -561,7 +561,8 @@ int hoszp_std(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, double* std, void
 
 static int f32_map(hoszp_ctx* ctx, int op, const float* x, const float* y, double s, float* out,
                    uint64_t n, void* stream) {
-  if (!ctx || !x || !out || (op == 1 && !y) || n == 0 || !aligned(x, 16) || !aligned(out, 16) ||
+  const bool two = op == 1 || op == 3 || op == 5;
+  if (!ctx || !x || !out || (two && !y) || n == 0 || !aligned(x, 16) || !aligned(out, 16) ||
       (y && !aligned(y, 16)))
     return HOSZP_ERR_ARG;
   DeviceScope scope(ctx->device);
@@ -583,6 +584,21 @@ int hoszp_f32_add_async(hoszp_ctx* ctx, const float* d_a, const float* d_b, floa
 int hoszp_f32_mul_async(hoszp_ctx* ctx, const float* d_x, double s, float* d_y, uint64_t n,
                         void* stream) {
   return f32_map(ctx, 2, d_x, nullptr, s, d_y, n, stream);
+}
+
+int hoszp_f32_sub_async(hoszp_ctx* ctx, const float* d_a, const float* d_b, float* d_y,
+                        uint64_t n, void* stream) {
+  return f32_map(ctx, 3, d_a, d_b, 0.0, d_y, n, stream);
+}
+
+int hoszp_f32_scalar_add_async(hoszp_ctx* ctx, const float* d_x, double s, float* d_y,
+                               uint64_t n, void* stream) {
+  return f32_map(ctx, 4, d_x, nullptr, s, d_y, n, stream);
+}
+
+int hoszp_f32_hadamard_async(hoszp_ctx* ctx, const float* d_a, const float* d_b, float* d_y,
+                             uint64_t n, void* stream) {
+  return f32_map(ctx, 5, d_a, d_b, 0.0, d_y, n, stream);
 }
 
 static int f32_reduce(hoszp_ctx* ctx, const float* x, uint64_t n, bool variance,

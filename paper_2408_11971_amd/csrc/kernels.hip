@@ -2447,15 +2447,33 @@ __global__ void __launch_bounds__(kThreads) k_f32_map(int op, const float* x, co
     } else if (op == 1) {
       const float4 b = y4[k];
       r = make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w);
-    } else {
+    } else if (op == 2) {
       r = make_float4(float(double(a.x) * s), float(double(a.y) * s), float(double(a.z) * s),
                       float(double(a.w) * s));
+    } else if (op == 3) {
+      const float4 b = y4[k];
+      r = make_float4(a.x - b.x, a.y - b.y, a.z - b.z, a.w - b.w);
+    } else if (op == 4) {
+      r = make_float4(float(double(a.x) + s), float(double(a.y) + s), float(double(a.z) + s),
+                      float(double(a.w) + s));
+    } else {
+      const float4 b = y4[k];
+      r = make_float4(a.x * b.x, a.y * b.y, a.z * b.z, a.w * b.w);
     }
     o4[k] = r;
   }
   for (uint64_t i = 4 * n4 + gt; i < n; i += stride) {
     const float a = x[i];
-    out[i] = op == 0 ? -a : (op == 1 ? a + y[i] : float(double(a) * s));
+    float r;
+    switch (op) {
+      case 0: r = -a; break;
+      case 1: r = a + y[i]; break;
+      case 2: r = float(double(a) * s); break;
+      case 3: r = a - y[i]; break;
+      case 4: r = float(double(a) + s); break;
+      default: r = a * y[i]; break;
+    }
+    out[i] = r;
   }
 }
 

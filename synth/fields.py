@@ -9,7 +9,8 @@ seeded random field with a comparable structure:
                        falls as k^-5/3 (turbulence-like, like Miranda).
 * ``climate_steps`` -- 2-D lat/lon climate-like steps (like CESM-ATM): smooth
                        latitude-dependent mean, k^-5/3 noise, AR(1) in time,
-                       and a 2 % land mask of exact zeros.
+                       and a 2 % land mask of exact zeros (``climate_steps_device``:
+                       the same recipe built on a GPU for the 100-step sweep).
 * ``batch_specs`` / ``batch_field`` -- thousands of smooth-plus-noise fields of
                        log-uniform size and mixed dimensionality.
 
@@ -132,6 +133,47 @@ def climate_steps(nsteps: int = 100, ny: int = 1800, nx: int = 3600, seed: int =
         step = mu + 5.0 * noise
         step[land] = 0.0
         yield step.astype(np.float32)
+
+
+def _grf_2d_device(ny, nx, gen, amp_exponent, device):
+    import torch
+
+    white = torch.randn((ny, nx), generator=gen, device=device, dtype=torch.float64)
+    fy = torch.fft.fftfreq(ny, device=device, dtype=torch.float64) * ny
+    fx = torch.fft.rfftfreq(nx, device=device, dtype=torch.float64) * nx
+    k2 = fy.view(ny, 1) ** 2 + fx.view(1, -1) ** 2
+    k2[0, 0] = 1.0
+    filt = k2.pow(0.5 * amp_exponent)
+    filt[0, 0] = 0.0
+    f = torch.fft.irfft2(torch.fft.rfft2(white) * filt, s=(ny, nx))
+    return (f - f.mean()) / f.std()
+
+
+def climate_steps_device(nsteps: int = 100, ny: int = 1800, nx: int = 3600, seed: int = 5,
+                         mask_seed: int = 6, rho: float = 0.95, device=None):
+    """The ``climate_steps`` recipe generated on a torch device (float64
+    FFTs, torch generators seeded with `seed` and `mask_seed`, so values
+    differ from the host version): an (nsteps, ny * nx) float32 tensor."""
+    import torch
+
+    lat = torch.linspace(-0.5 * math.pi, 0.5 * math.pi, ny, dtype=torch.float64, device=device)
+    mu = (250.0 + 40.0 * torch.cos(lat) ** 2).view(ny, 1)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(mask_seed)
+    smooth = _grf_2d_device(ny, nx, gen, -3.0, device)
+    thr = torch.kthvalue(smooth.reshape(-1).cpu(), int(0.98 * ny * nx)).values.item()
+    land = smooth >= thr
+    gen.manual_seed(seed)
+    noise = _grf_2d_device(ny, nx, gen, -4.0 / 3.0, device)
+    scale = math.sqrt(1.0 - rho * rho)
+    out = torch.empty((nsteps, ny * nx), dtype=torch.float32, device=device)
+    for t in range(nsteps):
+        if t > 0:
+            noise = rho * noise + scale * _grf_2d_device(ny, nx, gen, -4.0 / 3.0, device)
+        step = mu + 5.0 * noise
+        step[land] = 0.0
+        out[t] = step.reshape(-1).to(torch.float32)
+    return out
 
 
 _REL_EBS = (1e-2, 1e-3, 1e-4)

@@ -279,6 +279,12 @@ def test_float32_workflow_ops(dev):
     assert np.array_equal(host(out), x + y)
     hz.f32_mul_async(gx, 1.7, out)
     assert np.array_equal(host(out), (x.astype(np.float64) * 1.7).astype(np.float32))
+    hz.f32_sub_async(gx, gy, out)
+    assert np.array_equal(host(out), x - y)
+    hz.f32_scalar_add_async(gx, -0.37, out)
+    assert np.array_equal(host(out), (x.astype(np.float64) - 0.37).astype(np.float32))
+    hz.f32_hadamard_async(gx, gy, out)
+    assert np.array_equal(host(out), x * y)
     res = hz.new_result(dev)
     hz.f32_mean_async(gx, res)
     m = hz.read_result(res)["value"]
@@ -303,6 +309,8 @@ def test_traditional_equals_homomorphic(dev):
     hz.f32_negate_async(dx, t)
     trad = host(hz.compress(t, eb, 32))
     assert np.array_equal(ref.decode_bins(trad), ref.decode_bins(host(hz.negate(cx))))
+    hz.f32_sub_async(dx, dy, t)
+    assert np.array_equal(host(hz.compress(t, eb, 32)), host(hz.sub(cx, cy)))
 
 
 # ------------------------------------------------------------ async chain
