@@ -26,6 +26,8 @@ constexpr uint64_t kMaxN = 4294967295ULL; // n < 2^32
 constexpr int kThreads = 256;
 // Smallest encoder tile: sizes the look-back status words (kMaxTiles).
 constexpr int kMinTileSegs = kThreads;
+// Segments (= threads) per tile of the single-field compress kernel.
+constexpr int kCompressTileSegs = 1024;
 
 // Decoders work per wave on "wave tiles" of kWaveSegs segments (2048 slots),
 // with no workgroup barrier between tiles.  The width pre-pass stores every

@@ -35,7 +35,7 @@ constexpr uint32_t kNone = 0xffffffffu;
 constexpr uint32_t kEpochLimit = 1u << 28;  // look-back epochs are 28-bit, never 0
 // Workgroup size (= segments per look-back tile) of the single-field
 // encoders: larger tiles halve the serial look-back steps.
-constexpr int kCompressThreads = 1024;
+constexpr int kCompressThreads = kCompressTileSegs;
 constexpr int kMulThreads = 1024;
 constexpr int kAddThreads = 1024;
 
