@@ -66,8 +66,16 @@ def parse():
                          "query streams over a device store of compressed fields")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--store-gb", type=float, default=40.0)
-    ap.add_argument("--serve-seconds", type=float, default=1.0,
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="arrival window per offered rate")
+    ap.add_argument("--leg-batch", type=int, default=1,
+                    help="default workload: also run the 4096-field batch (0 = skip)")
+    ap.add_argument("--leg-serve-gb", type=float, default=10.0,
+                    help="default workload: store size of the short serving leg (0 = skip)")
+    ap.add_argument("--leg-serve-seconds", type=float, default=2.0,
+                    help="default workload: arrival window per rate of the serving leg")
+    ap.add_argument("--leg-c1", type=int, default=1,
+                    help="default workload: also time the 2^20-element 1-D field (0 = skip)")
     ap.add_argument("--rates", default="1000,5000,20000,50000")
     ap.add_argument("--slots", type=int, default=8)
     return ap.parse_args()
@@ -362,9 +370,16 @@ def main():
         torch.cuda.empty_cache()
         climate = bench_climate(args, torch, hz, synth, ctx, dev)
 
+    c1 = run_c1(torch, hz, synth, ctx, dev) if args.leg_c1 else None
+
     cpu = None
     if args.cpu_sample > 0:
         cpu = cpu_baseline(A, B, ebs, min(args.cpu_sample, N), args.cpu_threads)
+    del A, B
+    torch.cuda.empty_cache()
+    batch = run_batch(args, 5, 2, False) if args.leg_batch and args.batch_count > 0 else None
+    serve = (run_serve(args, args.leg_serve_gb, args.leg_serve_seconds, args.rates, False)
+             if args.leg_serve_gb > 0 else None)
 
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1,
@@ -384,8 +399,50 @@ def main():
         "cpu_baseline": cpu,
         "ops": ops,
         "climate": climate,
+        "c1_1d": c1,
+        "batch": batch,
+        "serve": serve,
     }
     print(json.dumps(line), flush=True)
+
+
+def run_c1(torch, hz, synth, ctx, dev, reps=20):
+    """The 2^20-element 1-D field (sum of 8 sinusoids plus noise, seeds 1 and
+    2, eb = 1e-3 of the range, block 32): each op replayed `reps` times from
+    a graph.  4 MiB per field stays in the 256 MB last-level cache, so these
+    rates are cache-resident, not HBM figures."""
+    n = 1 << 20
+    a = synth.sinusoid_1d(n, seed=1)
+    b = synth.sinusoid_1d(n, seed=2)
+    eb = synth.rel_eb(a, 1e-3)
+    A = torch.from_numpy(a).to(dev)
+    B = torch.from_numpy(b).to(dev)
+    cap = hz.compress_bound(n, 32)
+    ca, cb, co = (torch.empty(cap, dtype=torch.uint8, device=dev) for _ in range(3))
+    dec = torch.empty(n, dtype=torch.float32, device=dev)
+    res = hz.new_result(dev)
+    hz.compress_async(A, eb, 32, ca, res, ctx)
+    C = hz.read_result(res, ctx)["out_bytes"]
+    hz.compress_async(B, eb, 32, cb, res, ctx)
+    Cb = hz.read_result(res, ctx)["out_bytes"]
+    sa, sb = ca[:C], cb[:Cb]
+    ops = {
+        "compress": (4 * n, lambda: hz.compress_async(A, eb, 32, ca, res, ctx)),
+        "decompress": (4 * n, lambda: hz.decompress_async(sa, dec, res, ctx)),
+        "negate": (4 * n, lambda: hz.negate_async(sa, co, res, ctx)),
+        "add": (8 * n, lambda: hz.add_async(sa, sb, co, res, ctx)),
+        "mean": (4 * n, lambda: hz.mean_async(sa, res, ctx)),
+        "variance": (4 * n, lambda: hz.variance_async(sa, res, ctx)),
+    }
+    out = {"n": n, "block": 32, "rel_eb": 1e-3, "cr": round(4 * n / C, 3),
+           "note": "cache-resident (4 MiB per field): not an HBM roofline row", "ops": {}}
+    for op, (raw, fn) in ops.items():
+        us = graph_us(torch, lambda: [fn() for _ in range(reps)], 3) / reps
+        out["ops"][op] = {"us": round(us, 2), "gbps_raw": round(raw / us / 1e3, 1)}
+    r = hz.read_result(res, ctx)
+    if r["code"] != 0:
+        raise RuntimeError(f"1-D field ops failed: {r['code']}")
+    return out
 
 
 def graph_us(torch, body, reps):
@@ -498,11 +555,11 @@ def bench_climate(args, torch, hz, synth, ctx, dev):
     return out
 
 
-def bench_batch(args):
+def run_batch(args, steps, warmup, with_cpu):
     """4096 fields of log-uniform size 4 KB..64 MB (seed 7), per-field relative
     bound 1e-2/1e-3/1e-4 of the field's range, autotuned block size and grid;
     one step = one replay of the captured batch launch (compress every field
-    and produce its mean and variance)."""
+    and produce its mean and variance).  Returns a summary dict."""
     import numpy as np
     import torch
 
@@ -528,7 +585,7 @@ def bench_batch(args):
     b = hz.Batch([(xs[i], ebs[i], 0, outs[i]) for i in range(len(xs))], tune_grid=True)
     plan_s = time.perf_counter() - t0
     info = b.info()
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         b.launch()
     torch.cuda.synchronize()
     res = b.results()
@@ -538,7 +595,7 @@ def bench_batch(args):
     tm = Timer(torch)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         tm.run("batch", b.launch)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -549,26 +606,41 @@ def bench_batch(args):
     alg = raw + out_total
     achieved = alg / us / 1e3
     blocks = {L: sum(1 for r in res if r["block"] == L) for L in (32, 64, 128)}
-    cpu = None
-    if args.cpu_sample > 0:
-        cpu = cpu_baseline_batch(specs, xs, ebs, res)
+    cpu = cpu_baseline_batch(specs, xs, ebs, res) if with_cpu else None
+    out = {"value": round(raw / us / 1e3, 1), "unit": "GB/s", "ms_per_batch": round(us / 1e3, 3),
+           "ms_per_step_wall": round(1000.0 * wall / steps, 3),
+           "workload": f"batch_{len(specs)}_fields_4KB-64MB_loguniform", "fields": len(specs),
+           "raw_bytes": raw, "stream_bytes": out_total, "cr": round(raw / out_total, 3),
+           "total_tiles": info["total_tiles"], "grid": info["grid"],
+           "tile_threads": info.get("tile_threads"), "blocks_chosen": blocks,
+           "plan_seconds": round(plan_s, 2),
+           "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                        "traffic": None, "kernel": "k_batch", "launches_per_step": 1,
+                        "bytes_per_launch": alg, "us_per_launch": round(us, 2),
+                        "events_include": "the kernel alone"},
+           "cpu_baseline": cpu}
+    b.close()
+    del arena, out_arena, xs, outs
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_batch(args):
+    r = run_batch(args, args.steps, args.warmup, args.cpu_sample > 0)
     line = {
-        "metric": "batched compress + mean/variance GB/s (raw)", "value": round(raw / us / 1e3, 1),
+        "metric": "batched compress + mean/variance GB/s (raw)", "value": r["value"],
         "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(1000.0 * wall / args.steps, 3), "higher_is_better": True,
+        "ms_per_step": r["ms_per_step_wall"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
         "dtype": "int32 bins (f64 quantization, int64/int128 sums)", "data": "synthetic",
-        "config": {"workload": f"batch_{len(specs)}_fields_4KB-64MB_loguniform", "fields": len(specs),
-                   "raw_bytes": raw, "stream_bytes": out_total, "cr": round(raw / out_total, 3),
-                   "total_tiles": info["total_tiles"], "grid": info["grid"],
-                   "blocks_chosen": blocks, "plan_seconds": round(plan_s, 2),
-                   "parallelism": "single_gpu"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_batch", "launches_per_step": 1, "bytes_per_launch": alg,
-                     "us_per_launch": round(us, 2), "events_include": "the kernel alone"},
-        "cpu_baseline": cpu,
+        "config": {k: r[k] for k in ("workload", "fields", "raw_bytes", "stream_bytes", "cr",
+                                     "total_tiles", "grid", "tile_threads", "blocks_chosen",
+                                     "plan_seconds")},
+        "roofline": r["roofline"],
+        "cpu_baseline": r["cpu_baseline"],
     }
+    line["config"]["parallelism"] = "single_gpu"
     print(json.dumps(line), flush=True)
 
 
@@ -600,14 +672,15 @@ def cpu_baseline_batch(specs, xs, ebs, res, budget_s=15.0):
 SERVE_MIX = (("mean", 0.3), ("variance", 0.3), ("add", 0.2), ("negate", 0.1), ("mul", 0.1))
 
 
-def bench_serve(args):
+def run_serve(args, store_gb, seconds, rates_s, with_cpu):
     """A device store of ~store_gb of compressed fields (replicas of the
     512^3 fields at the three bounds and of climate-like 1800x3600 steps at
     blocks 32/64/128, half the bytes each), queried by open-loop Poisson
     streams (seed 8) at each offered rate for serve_seconds with the mix
     mean 30 %, variance 30 %, add 20 % (partner from the same field group),
     negate 10 %, multiply 10 % (scalar U(-2, 2), seed 9), once on the
-    homomorphic path and once on the decompress-compute-recompress path."""
+    homomorphic path and once on the decompress-compute-recompress path.
+    Returns a summary dict."""
     import numpy as np
     import torch
 
@@ -633,7 +706,7 @@ def bench_serve(args):
         for L in (32, 64, 128):
             c = hz.compress(xs, eb, L).clone()
             base.append((c, hz.header_of(c), f"clim{t}_{L}"))
-    target = args.store_gb * 1e9
+    target = store_gb * 1e9
     entries = []
     for kind in ("grf", "clim"):
         group = [b for b in base if b[2].startswith(kind)]
@@ -656,14 +729,14 @@ def bench_serve(args):
     gid = [groups[e[2]] for e in entries]
     ops = [hz.OPS[m[0]] for m in SERVE_MIX]
     probs = np.array([m[1] for m in SERVE_MIX])
-    rates = [float(r) for r in args.rates.split(",")]
+    rates = [float(r) for r in rates_s.split(",")]
     rng = np.random.default_rng(8)
     srng = np.random.default_rng(9)
     traces = []
     for lam in rates:
-        gaps = rng.exponential(1.0 / lam, size=int(lam * args.serve_seconds * 1.5) + 16)
+        gaps = rng.exponential(1.0 / lam, size=int(lam * seconds * 1.5) + 16)
         arr = np.cumsum(gaps)
-        arr = arr[arr < args.serve_seconds]
+        arr = arr[arr < seconds]
         k = arr.size
         ent = rng.integers(len(entries), size=k)
         op = np.array(ops)[rng.choice(len(ops), size=k, p=probs)]
@@ -717,29 +790,41 @@ def bench_serve(args):
         h, t = row["homomorphic"], row["decompress_compute_recompress"]
         row["p99_speedup"] = round(t["p99_ms"] / h["p99_ms"], 2)
         row["qps_ratio"] = round(h["achieved_qps"] / t["achieved_qps"], 2)
-    cpu = None
-    if args.cpu_sample > 0:
-        cpu = cpu_baseline_serve(entries, traces[0])
+    cpu = cpu_baseline_serve(entries, traces[0]) if with_cpu else None
     achieved = alg_hom_top[0] / alg_hom_top[1] / 1e9
+    out = {"value": round(qps_hom_top, 1), "unit": "queries/s",
+           "workload": f"serve_store_{store_bytes / 1e9:.0f}GB_poisson",
+           "store_streams": len(entries), "store_bytes": store_bytes, "slots": args.slots,
+           "pool_bytes": pool, "seconds_per_rate": seconds, "mix": dict(SERVE_MIX),
+           "rates": line_rows,
+           "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                        "traffic": None,
+                        "kernel": "all kernels of the run at the highest rate (aggregate)",
+                        "launches_per_step": None, "bytes_per_launch": None,
+                        "us_per_launch": None, "events_include": "host clock over the whole run"},
+           "cpu_baseline": cpu}
+    del entries, base
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_serve(args):
+    r = run_serve(args, args.store_gb, args.serve_seconds, args.rates, args.cpu_sample > 0)
     line = {
         "metric": "serving queries/s at the highest offered rate (homomorphic), with p50/p99 "
                   "latency vs decompress-compute-recompress",
-        "value": round(qps_hom_top, 1), "unit": "queries/s", "n_gpus": 1,
-        "steps": len(rates), "warmup": 0, "ms_per_step": None, "higher_is_better": True,
+        "value": r["value"], "unit": "queries/s", "n_gpus": 1,
+        "steps": len(r["rates"]), "warmup": 0, "ms_per_step": None, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
         "dtype": "int32 bins (f64 quantization, int64/int128 sums)", "data": "synthetic",
-        "config": {"workload": f"serve_store_{store_bytes / 1e9:.0f}GB_poisson",
-                   "store_streams": len(entries), "store_bytes": store_bytes,
-                   "slots": args.slots, "pool_bytes": pool, "seconds_per_rate": args.serve_seconds,
-                   "mix": dict(SERVE_MIX), "parallelism": "single_gpu"},
-        "rates": line_rows,
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "all kernels of the run at the highest rate (aggregate)",
-                     "launches_per_step": None, "bytes_per_launch": None,
-                     "us_per_launch": None, "events_include": "host clock over the whole run"},
-        "cpu_baseline": cpu,
+        "config": {k: r[k] for k in ("workload", "store_streams", "store_bytes", "slots",
+                                     "pool_bytes", "seconds_per_rate", "mix")},
+        "rates": r["rates"],
+        "roofline": r["roofline"],
+        "cpu_baseline": r["cpu_baseline"],
     }
+    line["config"]["parallelism"] = "single_gpu"
     print(json.dumps(line), flush=True)
 
 
