@@ -612,7 +612,7 @@ def run_batch(args, steps, warmup, with_cpu):
            "workload": f"batch_{len(specs)}_fields_4KB-64MB_loguniform", "fields": len(specs),
            "raw_bytes": raw, "stream_bytes": out_total, "cr": round(raw / out_total, 3),
            "total_tiles": info["total_tiles"], "grid": info["grid"],
-           "tile_threads": info.get("tile_threads"), "blocks_chosen": blocks,
+           "tile_threads": info.get("threads"), "blocks_chosen": blocks,
            "plan_seconds": round(plan_s, 2),
            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

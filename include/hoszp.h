@@ -310,10 +310,17 @@ int hoszp_f32_variance_async(hoszp_ctx* ctx, const float* d_x, uint64_t n, hoszp
  *   - block size, for every field whose `block` is 0: each of 32, 64, 128 is
  *     tried on the field's first min(n, 2^20) elements and the smallest
  *     stream wins (ties go to the larger block);
- *   - launch width, with HOSZP_BATCH_TUNE_GRID: the whole batch is run at a
- *     few persistent grid sizes and the fastest is kept.
- * Both run the real kernels on the caller's data, so they write the output
- * buffers; the captured launch rewrites them. */
+ *   - launch shape, with HOSZP_BATCH_TUNE_GRID: the whole batch is run with
+ *     tiles of 1024 and of 512 segments (workgroup sizes), each at a few
+ *     persistent grid sizes, and the fastest pair is kept.  The choice is
+ *     remembered per batch shape (device compute units, field count, every
+ *     field's n and block size) in a JSON Lines cache file, one object
+ *     {"key", "threads", "grid", "ms"} per line, at $HOSZP_TUNE_CACHE (empty:
+ *     no cache), else $XDG_CACHE_HOME/hoszp/batch_tune.jsonl, else
+ *     ~/.cache/hoszp/batch_tune.jsonl; a plan of a known shape skips the
+ *     timing runs.  Cache read or write failures are ignored.
+ * The tuning runs the real kernels on the caller's data, so they write the
+ * output buffers; the captured launch rewrites them. */
 
 typedef struct hoszp_field {
   const float* d_x;  /* n float32 values, 16-byte aligned, caller-owned */
@@ -342,7 +349,7 @@ typedef struct hoszp_batch_info {
   uint64_t raw_bytes;   /* sum of 4 n over the fields */
   uint64_t device_bytes;/* device memory the plan holds */
   uint32_t grid;        /* persistent workgroups per launch */
-  uint32_t reserved;
+  uint32_t threads;     /* workgroup size = 32-element segments per work-list tile */
 } hoszp_batch_info;
 
 #define HOSZP_BATCH_TUNE_GRID 1u

@@ -59,7 +59,7 @@ class FieldResult(ctypes.Structure):
 class BatchInfo(ctypes.Structure):
     _fields_ = [("fields", ctypes.c_uint64), ("total_tiles", ctypes.c_uint64),
                 ("raw_bytes", ctypes.c_uint64), ("device_bytes", ctypes.c_uint64),
-                ("grid", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("grid", ctypes.c_uint32), ("threads", ctypes.c_uint32)]
 
 
 BATCH_TUNE_GRID = 1

@@ -7,7 +7,10 @@
 // memory and wait for the stream.
 
 #include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
+#include <sys/stat.h>
 
 #include <new>
 
@@ -715,6 +718,177 @@ int time_grid(hoszp_batch* b, int grid, hipStream_t st, float* ms) {
   return rc;
 }
 
+// Device state of a plan with tiles of `nt` segments (replacing any earlier
+// one): the field table, the work list (the field of every tile), zeroed
+// status words, counters and accumulators, look-back generation 1.
+int build_plan(hoszp_batch* b, const hoszp_field* fields, const uint32_t* blocks, uint64_t count,
+               uint32_t nt, hipStream_t st) {
+  if (b->d_mem) {
+    if (hipStreamSynchronize(st) != hipSuccess) return HOSZP_ERR_DEVICE;
+    (void)hipFree(b->d_mem);
+    b->d_mem = nullptr;
+  }
+  hz::BatchField* hf = new (std::nothrow) hz::BatchField[count];
+  if (!hf) return HOSZP_ERR_NOMEM;
+  uint64_t tiles = 0, raw = 0;
+  for (uint64_t i = 0; i < count; ++i) {
+    hz::Layout g;
+    hz::place(g, fields[i].n, blocks[i], fields[i].eb);
+    hf[i] = hz::BatchField{fields[i].d_x, static_cast<uint8_t*>(fields[i].d_out), fields[i].n,
+                           fields[i].eb, 1.0 / (2.0 * fields[i].eb), tiles, blocks[i], 0};
+    tiles += hz::batch_tiles(g, nt);
+    raw += 4 * fields[i].n;
+  }
+  b->raw_bytes = raw;
+  auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+  const size_t f_b = up(count * sizeof(hz::BatchField)), tf_b = up(tiles * sizeof(uint32_t));
+  const size_t st_b = up(tiles * sizeof(uint64_t)), ctrl_b = 256;
+  const size_t acc_b = up(count * hz::kBatchAccWords * sizeof(uint64_t));
+  const size_t res_b = up(count * sizeof(hoszp_field_result));
+  b->device_bytes = f_b + tf_b + st_b + ctrl_b + acc_b + res_b;
+  int rc = HOSZP_OK;
+  if (hipMalloc(&b->d_mem, b->device_bytes) != hipSuccess) {
+    b->d_mem = nullptr;
+    rc = HOSZP_ERR_NOMEM;
+  }
+  uint32_t* tf = nullptr;
+  if (rc == HOSZP_OK) {
+    uint8_t* q = static_cast<uint8_t*>(b->d_mem);
+    b->dev.fields = reinterpret_cast<hz::BatchField*>(q);
+    b->dev.tile_field = reinterpret_cast<uint32_t*>(q + f_b);
+    b->dev.st = reinterpret_cast<uint64_t*>(q + f_b + tf_b);
+    b->dev.ctrl = reinterpret_cast<uint32_t*>(q + f_b + tf_b + st_b);
+    b->dev.facc = reinterpret_cast<uint64_t*>(q + f_b + tf_b + st_b + ctrl_b);
+    b->dev.res = reinterpret_cast<hoszp_field_result*>(q + f_b + tf_b + st_b + ctrl_b + acc_b);
+    b->dev.total_tiles = tiles;
+    b->dev.threads = nt;
+    tf = new (std::nothrow) uint32_t[tiles];
+    if (!tf) rc = HOSZP_ERR_NOMEM;
+  }
+  if (rc == HOSZP_OK) {
+    uint64_t t = 0;
+    for (uint64_t i = 0; i < count; ++i) {
+      hz::Layout g;
+      hz::place(g, hf[i].n, hf[i].block, hf[i].eb);
+      for (uint64_t k = 0; k < hz::batch_tiles(g, nt); ++k) tf[t++] = uint32_t(i);
+    }
+    const uint32_t epoch1 = 1;
+    if (hipMemsetAsync(b->d_mem, 0, b->device_bytes, st) != hipSuccess ||
+        hipMemcpyAsync(b->dev.fields, hf, count * sizeof(hz::BatchField), hipMemcpyHostToDevice,
+                       st) != hipSuccess ||
+        hipMemcpyAsync(const_cast<uint32_t*>(b->dev.tile_field), tf, tiles * sizeof(uint32_t),
+                       hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(b->dev.ctrl + 2, &epoch1, sizeof epoch1, hipMemcpyHostToDevice, st) !=
+            hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      rc = HOSZP_ERR_DEVICE;
+  }
+  delete[] tf;
+  delete[] hf;
+  return rc;
+}
+
+// ---- tuning cache -----------------------------------------------------------
+//
+// The launch shape a tuned plan chose (tile threads and grid), remembered per
+// batch shape so that a later plan of the same shape skips the timing runs.
+// A JSON Lines file, one object per tuned shape:
+//   {"key": "<16 hex digits>", "threads": 1024, "grid": 512, "ms": 16.8}
+// at $HOSZP_TUNE_CACHE (an empty value disables the cache), else
+// $XDG_CACHE_HOME/hoszp/batch_tune.jsonl, else ~/.cache/hoszp/batch_tune.jsonl.
+// Later lines win; unreadable or malformed lines are ignored, and failure to
+// write is not an error.
+
+struct TuneChoice {
+  uint32_t threads;
+  int grid;
+  float ms;
+};
+
+// FNV-1a over the plan's shape: compute units, field count, every field's n
+// and block size, and a format tag.
+uint64_t batch_signature(const hoszp_field* fields, const uint32_t* blocks, uint64_t count,
+                         int cus) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&h](uint64_t v) {
+    for (int k = 0; k < 8; ++k) {
+      h ^= (v >> (8 * k)) & 0xffu;
+      h *= 1099511628211ull;
+    }
+  };
+  mix(0x484f535a42415431ull);  // "HOSZBAT1"
+  mix(uint64_t(cus));
+  mix(count);
+  for (uint64_t i = 0; i < count; ++i) {
+    mix(fields[i].n);
+    mix(blocks[i]);
+  }
+  return h;
+}
+
+bool tune_cache_path(char* path, size_t cap) {
+  const char* env = getenv("HOSZP_TUNE_CACHE");
+  if (env) {
+    if (!*env || strlen(env) + 1 > cap) return false;
+    strcpy(path, env);
+    return true;
+  }
+  const char* xdg = getenv("XDG_CACHE_HOME");
+  const char* home = getenv("HOME");
+  char dir[3072];
+  if (xdg && *xdg) {
+    if (snprintf(dir, sizeof dir, "%s/hoszp", xdg) >= int(sizeof dir)) return false;
+  } else if (home && *home) {
+    if (snprintf(dir, sizeof dir, "%s/.cache/hoszp", home) >= int(sizeof dir)) return false;
+  } else {
+    return false;
+  }
+  return snprintf(path, cap, "%s/batch_tune.jsonl", dir) < int(cap);
+}
+
+bool tune_cache_lookup(uint64_t key, TuneChoice* out) {
+  char path[4096];
+  if (!tune_cache_path(path, sizeof path)) return false;
+  FILE* f = fopen(path, "r");
+  if (!f) return false;
+  char line[512];
+  bool found = false;
+  while (fgets(line, sizeof line, f)) {
+    unsigned long long k = 0;
+    unsigned threads = 0;
+    int grid = 0;
+    float ms = 0.f;
+    if (sscanf(line, " {\"key\": \"%16llx\", \"threads\": %u, \"grid\": %d, \"ms\": %f",
+               &k, &threads, &grid, &ms) == 4 &&
+        k == key && grid > 0 &&
+        (threads == uint32_t(hz::kBatchThreads) || threads == uint32_t(hz::kBatchThreadsSmall))) {
+      *out = TuneChoice{threads, grid, ms};
+      found = true;
+    }
+  }
+  fclose(f);
+  return found;
+}
+
+void tune_cache_store(uint64_t key, const TuneChoice& c) {
+  char path[4096];
+  if (!tune_cache_path(path, sizeof path)) return;
+  // create the directory chain below the file (one or two missing levels)
+  char dir[4096];
+  strcpy(dir, path);
+  for (char* p = dir + 1; *p; ++p) {
+    if (*p != '/') continue;
+    *p = 0;
+    (void)mkdir(dir, 0755);
+    *p = '/';
+  }
+  FILE* f = fopen(path, "a");
+  if (!f) return;
+  fprintf(f, "{\"key\": \"%016llx\", \"threads\": %u, \"grid\": %d, \"ms\": %.4f}\n",
+          (unsigned long long)key, c.threads, c.grid, double(c.ms));
+  fclose(f);
+}
+
 }  // namespace
 
 int hoszp_batch_create(hoszp_ctx* ctx, const hoszp_field* fields, uint64_t count, uint32_t flags,
@@ -738,85 +912,45 @@ int hoszp_batch_create(hoszp_ctx* ctx, const hoszp_field* fields, uint64_t count
     return HOSZP_ERR_DEVICE;
 
   uint32_t* blocks = new (std::nothrow) uint32_t[count];
-  hz::BatchField* hf = new (std::nothrow) hz::BatchField[count];
-  if (!blocks || !hf) {
-    delete[] blocks;
-    delete[] hf;
-    return HOSZP_ERR_NOMEM;
-  }
+  if (!blocks) return HOSZP_ERR_NOMEM;
   int rc = tune_blocks(ctx, fields, count, blocks, st);
-  uint64_t tiles = 0, raw = 0;
-  for (uint64_t i = 0; i < count && rc == HOSZP_OK; ++i) {
-    hz::Layout g;
-    hz::place(g, fields[i].n, blocks[i], fields[i].eb);
-    hf[i] = hz::BatchField{fields[i].d_x, static_cast<uint8_t*>(fields[i].d_out), fields[i].n,
-                           fields[i].eb, 1.0 / (2.0 * fields[i].eb), tiles, blocks[i], 0};
-    tiles += hz::batch_tiles(g);
-    raw += 4 * fields[i].n;
-  }
-  delete[] blocks;
   hoszp_batch* b = rc == HOSZP_OK ? new (std::nothrow) hoszp_batch() : nullptr;
   if (rc == HOSZP_OK && !b) rc = HOSZP_ERR_NOMEM;
-  uint32_t* tf = nullptr;
   if (rc == HOSZP_OK) {
     b->device = ctx->device;
     b->count = count;
-    b->raw_bytes = raw;
-    auto up = [](size_t x) { return (x + 255) / 256 * 256; };
-    const size_t f_b = up(count * sizeof(hz::BatchField)), tf_b = up(tiles * sizeof(uint32_t));
-    const size_t st_b = up(tiles * sizeof(uint64_t)), ctrl_b = 256;
-    const size_t acc_b = up(count * hz::kBatchAccWords * sizeof(uint64_t));
-    const size_t res_b = up(count * sizeof(hoszp_field_result));
-    b->device_bytes = f_b + tf_b + st_b + ctrl_b + acc_b + res_b;
-    if (hipMalloc(&b->d_mem, b->device_bytes) != hipSuccess) rc = HOSZP_ERR_NOMEM;
-    if (rc == HOSZP_OK) {
-      uint8_t* q = static_cast<uint8_t*>(b->d_mem);
-      b->dev.fields = reinterpret_cast<hz::BatchField*>(q);
-      b->dev.tile_field = reinterpret_cast<uint32_t*>(q + f_b);
-      b->dev.st = reinterpret_cast<uint64_t*>(q + f_b + tf_b);
-      b->dev.ctrl = reinterpret_cast<uint32_t*>(q + f_b + tf_b + st_b);
-      b->dev.facc = reinterpret_cast<uint64_t*>(q + f_b + tf_b + st_b + ctrl_b);
-      b->dev.res = reinterpret_cast<hoszp_field_result*>(q + f_b + tf_b + st_b + ctrl_b + acc_b);
-      b->dev.total_tiles = tiles;
-      tf = new (std::nothrow) uint32_t[tiles];
-      if (!tf) rc = HOSZP_ERR_NOMEM;
-    }
-    if (rc == HOSZP_OK) {
-      uint64_t t = 0;
-      for (uint64_t i = 0; i < count; ++i) {
-        hz::Layout g;
-        hz::place(g, hf[i].n, hf[i].block, hf[i].eb);
-        for (uint64_t k = 0; k < hz::batch_tiles(g); ++k) tf[t++] = uint32_t(i);
-      }
-      const uint32_t epoch1 = 1;
-      if (hipMemsetAsync(b->d_mem, 0, b->device_bytes, st) != hipSuccess ||
-          hipMemcpyAsync(b->dev.fields, hf, count * sizeof(hz::BatchField), hipMemcpyHostToDevice,
-                         st) != hipSuccess ||
-          hipMemcpyAsync(const_cast<uint32_t*>(b->dev.tile_field), tf, tiles * sizeof(uint32_t),
-                         hipMemcpyHostToDevice, st) != hipSuccess ||
-          hipMemcpyAsync(b->dev.ctrl + 2, &epoch1, sizeof epoch1, hipMemcpyHostToDevice, st) !=
-              hipSuccess ||
-          hipStreamSynchronize(st) != hipSuccess)
-        rc = HOSZP_ERR_DEVICE;
-    }
+    rc = build_plan(b, fields, blocks, count, hz::kBatchThreads, st);
   }
-  delete[] tf;
-  delete[] hf;
-  // launch width: the widest persistent grid, or the fastest of a few
+  // tile size and launch width: the widest persistent grid of 1024-thread
+  // tiles, or (tuning) the fastest of both tile sizes at a few grid sizes,
+  // remembered per batch shape in the tuning cache
   if (rc == HOSZP_OK) {
-    const int maxg = hz::batch_max_grid(cus);
-    b->grid = maxg;
+    b->grid = hz::batch_max_grid(cus, b->dev.threads);
     if (flags & HOSZP_BATCH_TUNE_GRID) {
-      const int cand[4] = {cus, 2 * cus, 3 * cus, maxg};
-      float best = 0.f;
-      for (int c = 0; c < 4 && rc == HOSZP_OK; ++c) {
-        if (cand[c] > maxg || (c > 0 && cand[c] == cand[c - 1])) continue;
-        float ms = 0.f;
-        rc = time_grid(b, cand[c], st, &ms);
-        if (rc == HOSZP_OK && (best == 0.f || ms < best)) best = ms, b->grid = cand[c];
+      const uint64_t key = batch_signature(fields, blocks, count, cus);
+      TuneChoice best{0, 0, 0.f};
+      if (!tune_cache_lookup(key, &best)) {
+        const uint32_t sizes[2] = {hz::kBatchThreads, hz::kBatchThreadsSmall};
+        for (int t = 0; t < 2 && rc == HOSZP_OK; ++t) {
+          if (b->dev.threads != sizes[t]) rc = build_plan(b, fields, blocks, count, sizes[t], st);
+          const int maxg = hz::batch_max_grid(cus, sizes[t]);
+          const int cand[4] = {cus, 2 * cus, 3 * cus, maxg};
+          for (int c = 0; c < 4 && rc == HOSZP_OK; ++c) {
+            if (cand[c] > maxg || (c > 0 && cand[c] == cand[c - 1])) continue;
+            float ms = 0.f;
+            rc = time_grid(b, cand[c], st, &ms);
+            if (rc == HOSZP_OK && (best.ms == 0.f || ms < best.ms))
+              best = TuneChoice{sizes[t], cand[c], ms};
+          }
+        }
+        if (rc == HOSZP_OK) tune_cache_store(key, best);
       }
+      if (rc == HOSZP_OK && b->dev.threads != best.threads)
+        rc = build_plan(b, fields, blocks, count, best.threads, st);
+      if (rc == HOSZP_OK) b->grid = best.grid;
     }
   }
+  delete[] blocks;
   if (rc == HOSZP_OK) {
     hipStream_t cap;
     if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) {
@@ -875,7 +1009,7 @@ int hoszp_batch_info_get(const hoszp_batch* b, hoszp_batch_info* out) {
   out->raw_bytes = b->raw_bytes;
   out->device_bytes = b->device_bytes;
   out->grid = uint32_t(b->grid);
-  out->reserved = 0;
+  out->threads = b->dev.threads;
   return HOSZP_OK;
 }
 

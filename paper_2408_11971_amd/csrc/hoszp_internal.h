@@ -161,12 +161,15 @@ struct BatchDev {
   uint32_t* ctrl;
   uint64_t* facc;
   hoszp_field_result* res;
+  uint32_t threads;  // workgroup size = segments per tile (kBatchThreads or kBatchThreadsSmall)
 };
 constexpr int kBatchAccWords = 8;  // accumulator words per field
-// Workgroup size of the batched compress = segments per work-list tile.
+// Workgroup sizes of the batched compress (= segments per work-list tile);
+// the autotuner picks one per plan.
 constexpr int kBatchThreads = 1024;
-inline __host__ __device__ uint64_t batch_tiles(const Layout& g) {
-  return (g.nseg + kBatchThreads - 1) / kBatchThreads;
+constexpr int kBatchThreadsSmall = 512;
+inline __host__ __device__ uint64_t batch_tiles(const Layout& g, uint32_t nt) {
+  return (g.nseg + nt - 1) / nt;
 }
 
 // Occupancy-derived persistent grid sizes, filled at context creation.
@@ -211,7 +214,7 @@ hipError_t launch_f32_reduce(const Scratch& s, const Grids& gr, const float* x, 
                              bool variance, hoszp_result* res, hipStream_t st);
 hipError_t launch_zero64(uint64_t* p, uint64_t n, hipStream_t st);
 hipError_t launch_batch(const BatchDev& b, int grid, hipStream_t st);
-int batch_max_grid(int num_cus);
+int batch_max_grid(int num_cus, uint32_t threads);
 hipError_t query_grids(Grids& gr, int num_cus);
 
 }  // namespace hz

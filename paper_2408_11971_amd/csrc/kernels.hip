@@ -984,11 +984,12 @@ struct BatchParams {
 // Adds a workgroup's sums and tile count of field f to the field's
 // accumulators; the workgroup that completes the field's tile count writes
 // the field's result record and clears the accumulators.  Contains barriers.
+template <int NT>
 __device__ __forceinline__ void batch_flush(const BatchParams& p, uint32_t f, const Layout& g,
                                             BinSums& sums, uint32_t bad, uint32_t count,
-                                            CompressShared<kBatchThreads>& sh) {
+                                            CompressShared<NT>& sh) {
   const int tid = threadIdx.x;
-  wg_sum_s_q<kBatchThreads>(sums.s, sums.ql, sums.qh, sh.rs, sh.rl, sh.rh);
+  wg_sum_s_q<NT>(sums.s, sums.ql, sums.qh, sh.rs, sh.rl, sh.rh);
   bad = uint32_t(__ballot(bad & ST_RANGE) ? ST_RANGE : 0u) |
         uint32_t(__ballot(bad & ST_NONFINITE) ? ST_NONFINITE : 0u);
   uint64_t* acc = p.facc + uint64_t(f) * F_WORDS;
@@ -1001,7 +1002,7 @@ __device__ __forceinline__ void batch_flush(const BatchParams& p, uint32_t f, co
     atomicAdd(reinterpret_cast<unsigned long long*>(&acc[F_QHI]),
               (unsigned long long)(sums.qh + carry));
   }
-  if (finish_arrive_n(reinterpret_cast<uint32_t*>(&acc[F_DONE]), count, uint32_t(batch_tiles(g)),
+  if (finish_arrive_n(reinterpret_cast<uint32_t*>(&acc[F_DONE]), count, uint32_t(batch_tiles(g, NT)),
                       &sh.flag) &&
       tid == 0) {
     const uint32_t status = uint32_t(ld_dev(&acc[F_STATUS]));
@@ -1020,8 +1021,10 @@ __device__ __forceinline__ void batch_flush(const BatchParams& p, uint32_t f, co
   sums = BinSums();
 }
 
-__global__ void __launch_bounds__(kBatchThreads) k_batch(BatchParams p) {
-  __shared__ CompressShared<kBatchThreads> sh;
+template <int NT>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
+k_batch(BatchParams p) {
+  __shared__ CompressShared<NT> sh;
   const int tid = threadIdx.x;
   const uint32_t epoch = uni32(ld_dev32(&p.ctrl[B_EPOCH]));
   uint32_t next = 0;
@@ -1037,7 +1040,7 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch(BatchParams p) {
     const uint64_t t = uni64(sh.ticket);
     const uint32_t f = t < p.total_tiles ? uni32(p.tile_field[t]) : kNone;
     if (f != cur && cur != kNone) {
-      batch_flush(p, cur, gc, sums, bad, count, sh);
+      batch_flush<NT>(p, cur, gc, sums, bad, count, sh);
       count = 0;
       bad = 0;
     }
@@ -1051,26 +1054,26 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch(BatchParams p) {
     uint64_t words = 0;
     switch (g.spb) {
       case 1:
-        words = compress_tile<1, true, kBatchThreads>(fd.x, fd.out, g, fd.eb, fd.inv2e, tile, p.st + fd.tile0,
+        words = compress_tile<1, true, NT>(fd.x, fd.out, g, fd.eb, fd.inv2e, tile, p.st + fd.tile0,
                                        epoch, sh, bad, sums, &p.ctrl[B_TICKET], next);
         break;
       case 2:
-        words = compress_tile<2, true, kBatchThreads>(fd.x, fd.out, g, fd.eb, fd.inv2e, tile, p.st + fd.tile0,
+        words = compress_tile<2, true, NT>(fd.x, fd.out, g, fd.eb, fd.inv2e, tile, p.st + fd.tile0,
                                        epoch, sh, bad, sums, &p.ctrl[B_TICKET], next);
         break;
       default:  // 4: batches take blocks up to 128 (checked when planned)
-        words = compress_tile<4, true, kBatchThreads>(fd.x, fd.out, g, fd.eb, fd.inv2e, tile, p.st + fd.tile0,
+        words = compress_tile<4, true, NT>(fd.x, fd.out, g, fd.eb, fd.inv2e, tile, p.st + fd.tile0,
                                        epoch, sh, bad, sums, &p.ctrl[B_TICKET], next);
         break;
     }
     ++count;
-    if (tid == 0 && tile == batch_tiles(g) - 1)
+    if (tid == 0 && tile == batch_tiles(g, NT) - 1)
       st_dev(&p.facc[uint64_t(f) * F_WORDS + F_OUT], g.off_p + 4 * words);
   }
   if (finish_arrive_n(&p.ctrl[B_DONE], 1u, gridDim.x, &sh.flag)) {
     const bool wrap = epoch + 1 >= kEpochLimit;  // epochs wrap: clear every status word
     if (wrap)
-      for (uint64_t k = tid; k < p.total_tiles; k += kBatchThreads) p.st[k] = 0;
+      for (uint64_t k = tid; k < p.total_tiles; k += NT) p.st[k] = 0;
     if (tid == 0) {
       p.ctrl[B_TICKET] = 0;
       p.ctrl[B_DONE] = 0;
@@ -2670,14 +2673,23 @@ hipError_t launch_zero64(uint64_t* p, uint64_t n, hipStream_t st) {
 
 hipError_t launch_batch(const BatchDev& b, int grid, hipStream_t st) {
   BatchParams p{b.fields, b.tile_field, b.total_tiles, b.st, b.ctrl, b.facc, b.res};
-  hipLaunchKernelGGL(k_batch, dim3(uint32_t(grid)), dim3(kBatchThreads), 0, st, p);
+  if (b.threads == kBatchThreadsSmall)
+    hipLaunchKernelGGL(k_batch<kBatchThreadsSmall>, dim3(uint32_t(grid)), dim3(kBatchThreadsSmall),
+                       0, st, p);
+  else
+    hipLaunchKernelGGL(k_batch<kBatchThreads>, dim3(uint32_t(grid)), dim3(kBatchThreads), 0, st, p);
   return hipGetLastError();
 }
 
-int batch_max_grid(int num_cus) {
+int batch_max_grid(int num_cus, uint32_t threads) {
   int occ = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch, kBatchThreads, 0) != hipSuccess)
-    return num_cus;
+  const hipError_t e =
+      threads == kBatchThreadsSmall
+          ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch<kBatchThreadsSmall>,
+                                                         kBatchThreadsSmall, 0)
+          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch<kBatchThreads>,
+                                                         kBatchThreads, 0);
+  if (e != hipSuccess) return num_cus;
   return num_cus * (occ < 1 ? 1 : occ);
 }
 

@@ -223,3 +223,53 @@ def test_batch_full_size_sampled(dev):
         c = hz.compress(xs[i], ebs[i], res[i]["block"])
         assert torch.equal(c, outs[i][:res[i]["out_bytes"]]), f"field {i}"
         assert hz.mean(c) == res[i]["mean"] and hz.variance(c) == res[i]["variance"]
+
+
+def fnv_signature(ns, blocks, cus):
+    """The plan-shape key of the tuning cache (FNV-1a over little-endian
+    64-bit words: tag, compute units, field count, then n and block of every
+    field)."""
+    h = 1469598103934665603
+    words = [0x484F535A42415431, cus, len(ns)]
+    for n, L in zip(ns, blocks):
+        words += [n, L]
+    for v in words:
+        for k in range(8):
+            h ^= (v >> (8 * k)) & 0xFF
+            h = (h * 1099511628211) & 0xFFFFFFFFFFFFFFFF
+    return h
+
+
+@pytest.mark.parametrize("threads", [512, 1024])
+def test_tuned_plan_tile_sizes_and_cache(dev, tmp_path, monkeypatch, threads):
+    """Both tile sizes the autotuner chooses between give the oracle's streams;
+    a tuned plan records its choice in the cache file, and a plan of the same
+    shape takes the recorded choice (here forced to `threads`)."""
+    print(f"case batch tile threads={threads}", flush=True)
+    sizes = [1000, 33000, 70001, 5, 262144 + 77, 1 << 20, 40000]
+    fields = make_fields(31, sizes, [32, 64, 128, 32, 64, 128, 32])
+    cache = tmp_path / "tune.jsonl"
+    monkeypatch.setenv("HOSZP_TUNE_CACHE", str(cache))
+    b, gx, outs = run_batch(fields, dev, tune_grid=True)
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1
+    rec = __import__("json").loads(lines[0])
+    info = b.info()
+    assert info["threads"] == rec["threads"] and info["grid"] == rec["grid"]
+    b.launch()
+    check_against_oracle(fields, b.results(), outs)
+    b.close()
+    # force the other tile size through the cache
+    cus = torch.cuda.get_device_properties(dev).multi_processor_count
+    key = fnv_signature([x.size for x, _, _ in fields], [L for _, _, L in fields], cus)
+    assert f"{key:016x}" == rec["key"]
+    with open(cache, "a") as f:
+        f.write('{"key": "%016x", "threads": %d, "grid": %d, "ms": 1.0}\n' % (key, threads, cus))
+    b, gx, outs = run_batch(fields, dev, tune_grid=True)
+    info = b.info()
+    assert info["threads"] == threads and info["grid"] == cus
+    assert len(cache.read_text().splitlines()) == 2  # read, not tuned again
+    for _ in range(2):
+        b.launch()
+        check_against_oracle(fields, b.results(), outs)
+    b.close()
