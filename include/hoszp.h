@@ -75,6 +75,7 @@ extern "C" {
 #define HOSZP_ERR_DEVICE 7    /* a HIP runtime call failed */
 #define HOSZP_ERR_NOMEM 8     /* device or pinned allocation failed */
 #define HOSZP_ERR_LIMIT 9     /* input larger than an allocation-free entry point allows */
+#define HOSZP_ERR_TIMEOUT 10  /* an encoder gave up waiting on its look-back (see hoszp_set_wait_limit) */
 
 /* Outcome of an asynchronous call, written by the GPU into caller-owned
  * device memory (64 bytes, 8-byte aligned).
@@ -115,6 +116,22 @@ int hoszp_ctx_create(int device, hoszp_ctx** out);
  * every stream that used it). NULL is accepted. */
 int hoszp_ctx_destroy(hoszp_ctx* ctx);
 
+/* Bound the look-back waits of the encoders (compress, add, sub, mul,
+ * Hadamard product, and batches created afterwards) launched on `ctx` from
+ * now on.  An encoder tile finds its payload offset by waiting for the tiles
+ * before it (a decoupled look-back, the device-wide form of the prefix sum of
+ * block sizes that the byte layout of Sec. IV-A needs); a tile that polls its
+ * predecessors `polls` times without finishing gives up, the launch still
+ * drains, and its result reports HOSZP_ERR_TIMEOUT with the output invalid.
+ * Predecessors are always running workgroups, so a correct call never comes
+ * near the default (2^24 polls, seconds); the limit turns a wait that cannot
+ * end (for instance overlapping calls that share scratch, which the
+ * allocation-free entry point forbids) into an error instead of a hang.
+ * 0 makes every tile but the first give up at once, which forces the error
+ * path from the host.  Not thread-safe against calls enqueueing on `ctx`.
+ * Returns HOSZP_OK, or HOSZP_ERR_ARG for a NULL context. */
+int hoszp_set_wait_limit(hoszp_ctx* ctx, uint32_t polls);
+
 /* Worst-case stream size for n elements (every block at width 32); 0 when n or
  * block is invalid.  Output buffers of compress/add/mul must be at least this
  * large. */
@@ -126,7 +143,7 @@ size_t hoszp_compress_bound(uint64_t n, uint32_t block);
 int hoszp_parse_header(const void* h_header, size_t header_bytes, hoszp_info* out);
 
 /* Map a status bit mask (hoszp_result.status) to one code, by precedence
- * ARG, FORMAT, MISMATCH, CAPACITY, NONFINITE, RANGE. */
+ * TIMEOUT, ARG, FORMAT, MISMATCH, CAPACITY, NONFINITE, RANGE. */
 int hoszp_status_code(uint32_t status_mask);
 
 /* Human-readable name of a status code. */

@@ -16,8 +16,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhoszp.so")
 
 OK, ERR_ARG, ERR_NONFINITE, ERR_RANGE, ERR_FORMAT, ERR_MISMATCH, ERR_CAPACITY, ERR_DEVICE, \
-    ERR_NOMEM, ERR_LIMIT = range(10)
+    ERR_NOMEM, ERR_LIMIT, ERR_TIMEOUT = range(11)
 NOALLOC_MAX_N = 1 << 28
+DEFAULT_WAIT_LIMIT = 1 << 24
 RESULT_BYTES = 64
 
 
@@ -96,6 +97,7 @@ _VP, _SZ, _U64, _U32, _DBL, _INT = (ctypes.c_void_p, ctypes.c_size_t, ctypes.c_u
 _SIGNATURES = {
     "hoszp_ctx_create": (_INT, [_INT, ctypes.POINTER(_VP)]),
     "hoszp_ctx_destroy": (_INT, [_VP]),
+    "hoszp_set_wait_limit": (_INT, [_VP, _U32]),
     "hoszp_compress_bound": (_SZ, [_U64, _U32]),
     "hoszp_parse_header": (_INT, [_VP, _SZ, ctypes.POINTER(Info)]),
     "hoszp_status_code": (_INT, [_U32]),
@@ -221,6 +223,10 @@ class Context:
         h = _VP()
         _check(_lib().hoszp_ctx_create(device, ctypes.byref(h)), "ctx_create")
         self.handle = h
+
+    def set_wait_limit(self, polls: int):
+        """Poll limit of this context's encoder look-back waits (0: give up at once)."""
+        _check(_lib().hoszp_set_wait_limit(self.handle, int(polls)), "set_wait_limit")
 
     def close(self):
         if getattr(self, "handle", None) and _LIB is not None:

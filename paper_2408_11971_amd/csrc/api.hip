@@ -109,8 +109,11 @@ hz::MulScalar mul_split(double s) {
 extern "C" {
 
 int hoszp_status_code(uint32_t m) {
-  static const int order[] = {HOSZP_ERR_ARG, HOSZP_ERR_FORMAT, HOSZP_ERR_MISMATCH,
-                              HOSZP_ERR_CAPACITY, HOSZP_ERR_NONFINITE, HOSZP_ERR_RANGE};
+  // a launch that gave up on its look-back reports that first: the other
+  // bits it latched may be consequences of the prefix it could not finish
+  static const int order[] = {HOSZP_ERR_TIMEOUT, HOSZP_ERR_ARG, HOSZP_ERR_FORMAT,
+                              HOSZP_ERR_MISMATCH, HOSZP_ERR_CAPACITY, HOSZP_ERR_NONFINITE,
+                              HOSZP_ERR_RANGE};
   for (int code : order)
     if (m & (1u << code)) return code;
   return m ? HOSZP_ERR_DEVICE : HOSZP_OK;
@@ -127,6 +130,7 @@ const char* hoszp_strerror(int code) {
     case HOSZP_ERR_CAPACITY: return "output buffer too small";
     case HOSZP_ERR_DEVICE: return "HIP runtime error";
     case HOSZP_ERR_NOMEM: return "out of memory";
+    case HOSZP_ERR_TIMEOUT: return "look-back wait exceeded the context's poll limit; output invalid";
     case HOSZP_ERR_LIMIT: return "input larger than the allocation-free entry point allows (n <= 2^28)";
     default: return "unknown status";
   }
@@ -214,6 +218,7 @@ int hoszp_ctx_create(int device, hoszp_ctx** out) {
   ctx->d_res = reinterpret_cast<hoszp_result*>(q);
   ctx->s.max_tiles = kMaxTiles;
   ctx->s.max_part = kMaxPart;
+  ctx->s.wait_limit = hz::kDefaultWaitLimit;
   if (hipMemset(ctx->d_mem, 0, bytes) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
     (void)hipHostFree(ctx->h_res);
     (void)hipFree(ctx->d_mem);
@@ -232,6 +237,12 @@ int hoszp_ctx_destroy(hoszp_ctx* ctx) {
   if (hipFree(ctx->d_mem) != hipSuccess) rc = HOSZP_ERR_DEVICE;
   delete ctx;
   return rc;
+}
+
+int hoszp_set_wait_limit(hoszp_ctx* ctx, uint32_t polls) {
+  if (!ctx) return HOSZP_ERR_ARG;
+  ctx->s.wait_limit = polls;
+  return HOSZP_OK;
 }
 
 int hoszp_result_wait(hoszp_ctx* ctx, const hoszp_result* d_res, hoszp_result* h_out,
@@ -919,6 +930,7 @@ int hoszp_batch_create(hoszp_ctx* ctx, const hoszp_field* fields, uint64_t count
   if (rc == HOSZP_OK) {
     b->device = ctx->device;
     b->count = count;
+    b->dev.wait_limit = ctx->s.wait_limit;
     rc = build_plan(b, fields, blocks, count, hz::kBatchThreads, st);
   }
   // tile size and launch width: the widest persistent grid of 1024-thread

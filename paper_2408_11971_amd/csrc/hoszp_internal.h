@@ -46,6 +46,7 @@ constexpr uint32_t ST_RANGE = 1u << HOSZP_ERR_RANGE;
 constexpr uint32_t ST_FORMAT = 1u << HOSZP_ERR_FORMAT;
 constexpr uint32_t ST_MISMATCH = 1u << HOSZP_ERR_MISMATCH;
 constexpr uint32_t ST_CAPACITY = 1u << HOSZP_ERR_CAPACITY;
+constexpr uint32_t ST_TIMEOUT = 1u << HOSZP_ERR_TIMEOUT;
 
 // Section placement of a stream with n elements in blocks of L.
 struct Layout {
@@ -105,7 +106,13 @@ struct Scratch {
   TileIndex idx[2];     // width pre-pass of input stream A and B
   uint32_t max_tiles;   // capacity of the per-tile status words (and / 64 chunks)
   uint32_t max_part;    // capacity of `part`
+  uint32_t wait_limit;  // polls an encoder tile may spend on its look-back
+                        // before it gives up with ST_TIMEOUT
 };
+// Default look-back poll limit: a poll is one device-coherent load (about a
+// microsecond) plus a short sleep, so a launch gives up after seconds, far
+// beyond any wait on running predecessors (tens of microseconds).
+constexpr uint32_t kDefaultWaitLimit = 1u << 24;
 
 // Scalar multiplier, classified on the host (see mul_split()).
 struct MulScalar {
@@ -162,6 +169,7 @@ struct BatchDev {
   uint64_t* facc;
   hoszp_field_result* res;
   uint32_t threads;  // workgroup size = segments per tile (kBatchThreads or kBatchThreadsSmall)
+  uint32_t wait_limit;  // look-back poll limit of the launch
 };
 constexpr int kBatchAccWords = 8;  // accumulator words per field
 // Workgroup sizes of the batched compress (= segments per work-list tile);

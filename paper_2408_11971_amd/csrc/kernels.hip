@@ -296,7 +296,8 @@ struct LbShared {
   uint32_t first_wait[NT / 64];
   uint64_t part[NT / 64];
   uint64_t near_sum;
-  uint32_t near_found;
+  uint32_t near_found;  // 0: keep searching, 1: inclusive prefix found, 2: gave up
+  uint32_t polls;
 };
 
 // Decoupled look-back: exclusive prefix over tiles of the per-tile `agg`.
@@ -315,15 +316,33 @@ __device__ __forceinline__ void lb_publish(uint64_t* st, uint64_t tile, uint64_t
   if (threadIdx.x == 0) st_dev(&st[tile], lb_word(epoch, tile == 0 ? kLbInc : kLbAgg, agg));
 }
 
-// Contains barriers (except for tile 0, which returns at once).
+// The wait is bounded: after `limit` unsuccessful polls (phase 1 and 2
+// together) the tile gives up, ORs ST_TIMEOUT into `bad`, takes what it has
+// summed as its prefix and publishes as usual, so the launch still drains and
+// every later wait ends.  A prefix taken this way is at most the true one, so
+// the tile's stores stay inside the stream's worst-case bound; the launch's
+// output is invalid and the error says so.  With limit 0 every tile but the
+// first gives up without polling.  Contains barriers (except for tile 0, which
+// returns at once).
 template <int NT = kThreads>
 __device__ __forceinline__ uint64_t lb_wait(uint64_t* st, uint64_t tile, uint64_t agg,
-                                            uint32_t epoch, LbShared<NT>& sh) {
+                                            uint32_t epoch, LbShared<NT>& sh, uint32_t limit,
+                                            uint32_t& bad) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (tile == 0) return 0;
+  uint32_t polls = 0;
   if (wave == 0) {
     const int64_t idx = int64_t(tile) - 1 - lane;
     for (;;) {
+      if (polls >= limit) {  // wave-uniform
+        if (lane == 0) {
+          sh.near_sum = 0;
+          sh.near_found = 2u;
+          sh.polls = polls;
+        }
+        break;
+      }
+      ++polls;
       bool ready = true, inc = true;
       uint64_t val = 0;
       if (idx >= 0) {
@@ -344,17 +363,25 @@ __device__ __forceinline__ uint64_t lb_wait(uint64_t* st, uint64_t tile, uint64_
       if (lane == 0) {
         sh.near_sum = part;
         sh.near_found = incm ? 1u : 0u;
+        sh.polls = polls;
       }
       break;
     }
   }
   __syncthreads();
   uint64_t excl = uni64(sh.near_sum);
-  const bool found = uni32(sh.near_found) != 0;
+  const uint32_t found = uni32(sh.near_found);
+  polls = uni32(sh.polls);
   __syncthreads();
+  if (found == 2u) bad |= ST_TIMEOUT;
   if (!found) {
     int64_t base = int64_t(tile) - 64;  // the window covers tiles base-1-tid
     for (;;) {
+      if (polls >= limit) {  // workgroup-uniform
+        bad |= ST_TIMEOUT;
+        break;
+      }
+      ++polls;
       const int64_t idx = base - 1 - tid;
       uint32_t fi = kNone, fw = kNone;
       uint64_t val = 0;
@@ -838,7 +865,7 @@ struct CompressShared {
 template <int SPB, bool STATS, int NT = kThreads>
 __device__ __forceinline__ uint64_t compress_tile(const float* x, uint8_t* out, const Layout& g, double eb,
                                   double inv2e, uint64_t tile, uint64_t* st, uint32_t epoch,
-                                  CompressShared<NT>& sh, uint32_t& bad, BinSums& sums,
+                                  uint32_t limit, CompressShared<NT>& sh, uint32_t& bad, BinSums& sums,
                                   uint32_t* ticket, uint32_t& next) {
   constexpr uint32_t L = SPB * 32;
   const int tid = threadIdx.x;
@@ -900,7 +927,7 @@ __device__ __forceinline__ uint64_t compress_tile(const float* x, uint8_t* out, 
     }
     reinterpret_cast<uint32_t*>(out + g.off_s)[seg] = bswap32(sgn);
   }
-  const uint64_t base = lb_wait<NT>(st, tile, tile_words, epoch, sh.lb);
+  const uint64_t base = lb_wait<NT>(st, tile, tile_words, epoch, sh.lb, limit, bad);
   // The next tile is requested now: its ticket is held only while this tile
   // stores, never while this tile waits on its predecessors.
   if (tid == 0) next = atomicAdd(ticket, 1u);
@@ -928,7 +955,8 @@ __global__ void __launch_bounds__(NT) k_compress(CompressParams p) {
     const uint64_t tile = uni64(sh.ticket);
     if (tile >= ntiles) break;
     const uint64_t words =
-        compress_tile<SPB, false, NT>(p.x, p.out, g, p.eb, p.inv2e, tile, p.s.st_out, epoch, sh,
+        compress_tile<SPB, false, NT>(p.x, p.out, g, p.eb, p.inv2e, tile, p.s.st_out, epoch,
+                                      p.s.wait_limit, sh,
                                   bad, none, &p.s.ctrl[C_TICKET], next);
     if (tid == 0 && tile == ntiles - 1) st_dev(&p.s.acc[A_OUT], g.off_p + 4 * words);
   }
@@ -979,6 +1007,7 @@ struct BatchParams {
   uint32_t* ctrl;              // B_* counters
   uint64_t* facc;              // F_WORDS words per field
   hoszp_field_result* res;     // one record per field
+  uint32_t wait_limit;         // look-back poll limit (see lb_wait)
 };
 
 // Adds a workgroup's sums and tile count of field f to the field's
@@ -991,7 +1020,8 @@ __device__ __forceinline__ void batch_flush(const BatchParams& p, uint32_t f, co
   const int tid = threadIdx.x;
   wg_sum_s_q<NT>(sums.s, sums.ql, sums.qh, sh.rs, sh.rl, sh.rh);
   bad = uint32_t(__ballot(bad & ST_RANGE) ? ST_RANGE : 0u) |
-        uint32_t(__ballot(bad & ST_NONFINITE) ? ST_NONFINITE : 0u);
+        uint32_t(__ballot(bad & ST_NONFINITE) ? ST_NONFINITE : 0u) |
+        uint32_t(__ballot(bad & ST_TIMEOUT) ? ST_TIMEOUT : 0u);
   uint64_t* acc = p.facc + uint64_t(f) * F_WORDS;
   if ((tid & 63) == 0 && bad) atomicOr(reinterpret_cast<unsigned int*>(&acc[F_STATUS]), bad);
   if (tid == 0) {
@@ -1055,15 +1085,15 @@ k_batch(BatchParams p) {
     switch (g.spb) {
       case 1:
         words = compress_tile<1, true, NT>(fd.x, fd.out, g, fd.eb, fd.inv2e, tile, p.st + fd.tile0,
-                                       epoch, sh, bad, sums, &p.ctrl[B_TICKET], next);
+                                       epoch, p.wait_limit, sh, bad, sums, &p.ctrl[B_TICKET], next);
         break;
       case 2:
         words = compress_tile<2, true, NT>(fd.x, fd.out, g, fd.eb, fd.inv2e, tile, p.st + fd.tile0,
-                                       epoch, sh, bad, sums, &p.ctrl[B_TICKET], next);
+                                       epoch, p.wait_limit, sh, bad, sums, &p.ctrl[B_TICKET], next);
         break;
       default:  // 4: batches take blocks up to 128 (checked when planned)
         words = compress_tile<4, true, NT>(fd.x, fd.out, g, fd.eb, fd.inv2e, tile, p.st + fd.tile0,
-                                       epoch, sh, bad, sums, &p.ctrl[B_TICKET], next);
+                                       epoch, p.wait_limit, sh, bad, sums, &p.ctrl[B_TICKET], next);
         break;
     }
     ++count;
@@ -1923,7 +1953,8 @@ __global__ void __launch_bounds__(NT) k_add(AddParams p) {
       }
       reinterpret_cast<uint32_t*>(p.out + g.off_s)[seg] = bswap32(sgn);
     }
-    const uint64_t base_z = lb_wait<NT>(p.s.st_out, tile, tw_z, epoch, s_lb);
+    const uint64_t base_z = lb_wait<NT>(p.s.st_out, tile, tw_z, epoch, s_lb, p.s.wait_limit, bad);
+    if (tid == 0) latch(p.s, bad & ST_TIMEOUT);
     if (tid == 0) next = atomicAdd(&p.s.ctrl[C_TICKET], 1u);
     __syncthreads();
     uint32_t* Pz = reinterpret_cast<uint32_t*>(p.out + g.off_p) + base_z;
@@ -2113,7 +2144,8 @@ __global__ void __launch_bounds__(NT) k_mul(MulParams p) {
       }
       reinterpret_cast<uint32_t*>(p.out + g.off_s)[seg] = bswap32(sgn);
     }
-    const uint64_t base_z = lb_wait<NT>(p.s.st_out, tile, tw_z, epoch, s_lb);
+    const uint64_t base_z = lb_wait<NT>(p.s.st_out, tile, tw_z, epoch, s_lb, p.s.wait_limit, bad);
+    if (tid == 0) latch(p.s, bad & ST_TIMEOUT);
     if (tid == 0) next = atomicAdd(&p.s.ctrl[C_TICKET], 1u);
     __syncthreads();
     uint32_t* Pz = reinterpret_cast<uint32_t*>(p.out + g.off_p) + base_z;
@@ -2384,7 +2416,8 @@ __global__ void __launch_bounds__(NT) k_bivar(BivarParams p) {
       }
       reinterpret_cast<uint32_t*>(p.out + g.off_s)[seg] = bswap32(sgn);
     }
-    const uint64_t base_z = lb_wait<NT>(p.s.st_out, tile, tw_z, epoch, s_lb);
+    const uint64_t base_z = lb_wait<NT>(p.s.st_out, tile, tw_z, epoch, s_lb, p.s.wait_limit, bad);
+    if (tid == 0) latch(p.s, bad & ST_TIMEOUT);
     if (tid == 0) next = atomicAdd(&p.s.ctrl[C_TICKET], 1u);
     __syncthreads();
     uint32_t* Pz = reinterpret_cast<uint32_t*>(p.out + g.off_p) + base_z;
@@ -2672,7 +2705,7 @@ hipError_t launch_zero64(uint64_t* p, uint64_t n, hipStream_t st) {
 }
 
 hipError_t launch_batch(const BatchDev& b, int grid, hipStream_t st) {
-  BatchParams p{b.fields, b.tile_field, b.total_tiles, b.st, b.ctrl, b.facc, b.res};
+  BatchParams p{b.fields, b.tile_field, b.total_tiles, b.st, b.ctrl, b.facc, b.res, b.wait_limit};
   if (b.threads == kBatchThreadsSmall)
     hipLaunchKernelGGL(k_batch<kBatchThreadsSmall>, dim3(uint32_t(grid)), dim3(kBatchThreadsSmall),
                        0, st, p);

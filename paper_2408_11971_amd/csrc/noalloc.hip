@@ -73,6 +73,7 @@ hz::Scratch scratch_of(uint64_t* p) {
   s.acc = p + 32;
   s.st_out = p + kCtrlWords;
   s.max_tiles = uint32_t(kLbWords);
+  s.wait_limit = hz::kDefaultWaitLimit;
   return s;
 }
 

@@ -81,6 +81,9 @@ def test_status_precedence(lib):
     assert hz.status_code(bit(hz.ERR_RANGE) | bit(hz.ERR_FORMAT)) == hz.ERR_FORMAT
     assert hz.status_code(bit(hz.ERR_CAPACITY) | bit(hz.ERR_MISMATCH)) == hz.ERR_MISMATCH
     assert hz.status_code(bit(hz.ERR_RANGE)) == hz.ERR_RANGE
+    # a look-back that gave up outranks what its invalid prefix caused
+    assert hz.status_code(bit(hz.ERR_TIMEOUT) | bit(hz.ERR_FORMAT) | bit(hz.ERR_ARG)) == hz.ERR_TIMEOUT
+    assert b"poll limit" in hz._lib().hoszp_strerror(hz.ERR_TIMEOUT)
 
 
 def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
