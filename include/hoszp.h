@@ -161,6 +161,16 @@ int hoszp_compress_async(hoszp_ctx* ctx, const float* d_x, uint64_t n, double eb
                          uint32_t block, void* d_out, size_t out_cap, hoszp_result* d_res,
                          void* stream);
 
+/* The float inputs compress accepts at error bound eb: the interval
+ * [*h_lo, *h_hi] of float32 values whose quantization bin (Eq. 3, evaluated
+ * as the kernels do: floor(((double)x + eb) * (1 / (2 eb))) in binary64)
+ * lies in [-(2^31-1), 2^31-1].  The bin is non-decreasing in x, so compress
+ * reports RANGE exactly when some finite input is outside the interval (and
+ * NONFINITE for NaN or infinity).  Both bounds are finite (0 is always
+ * inside).  Returns ARG for eb <= 0, a non-finite eb or a NULL pointer, else
+ * OK.  Host only; needs no device. */
+int hoszp_bin_range(double eb, float* h_lo, float* h_hi);
+
 /* Full decompression: d_x[i] = (float)((double)bin_i * 2 eb) for the stream's
  * n elements; n_cap is the capacity of d_x in elements (>= n). */
 int hoszp_decompress(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, float* d_x,

@@ -113,6 +113,7 @@ _SIGNATURES = {
     "hoszp_mul": (_INT, [_VP, _VP, _SZ, _DBL, _VP, _SZ, ctypes.POINTER(_SZ), _VP]),
     "hoszp_mul_async": (_INT, [_VP, _VP, _SZ, _DBL, _VP, _SZ, _VP, _VP]),
     "hoszp_mul_bins": (_INT, [_DBL, _VP, _VP, _U64]),
+    "hoszp_bin_range": (_INT, [_DBL, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
     "hoszp_sub": (_INT, [_VP, _VP, _SZ, _VP, _SZ, _VP, _SZ, ctypes.POINTER(_SZ), _VP]),
     "hoszp_sub_async": (_INT, [_VP, _VP, _SZ, _VP, _SZ, _VP, _SZ, _VP, _VP]),
     "hoszp_scalar_add": (_INT, [_VP, _VP, _SZ, _DBL, _VP, _SZ, ctypes.POINTER(_SZ), _VP]),
@@ -199,6 +200,14 @@ def parse_header(header: bytes) -> dict:
 
 def status_code(mask: int) -> int:
     return _lib().hoszp_status_code(mask)
+
+
+def bin_range(eb):
+    """(lo, hi): the float32 inputs whose bin at error bound eb is in range
+    (see hoszp_bin_range)."""
+    lo, hi = ctypes.c_float(0.0), ctypes.c_float(0.0)
+    _check(_lib().hoszp_bin_range(float(eb), ctypes.byref(lo), ctypes.byref(hi)), "bin_range")
+    return lo.value, hi.value
 
 
 def mul_bins(s: float, q):

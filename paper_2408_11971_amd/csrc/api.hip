@@ -442,6 +442,12 @@ int hoszp_mul(hoszp_ctx* ctx, const void* d_c, size_t c_bytes, double s, void* d
   return rc;
 }
 
+int hoszp_bin_range(double eb, float* h_lo, float* h_hi) {
+  if (!h_lo || !h_hi || !(eb > 0.0) || !isfinite(eb)) return HOSZP_ERR_ARG;
+  hz::bin_range_floats(eb, 1.0 / (2.0 * eb), *h_lo, *h_hi);
+  return HOSZP_OK;
+}
+
 int hoszp_mul_bins(double s, const int32_t* h_q, int32_t* h_out, uint64_t n) {
   if ((n && (!h_q || !h_out)) || !isfinite(s)) return HOSZP_ERR_ARG;
   const double sc = mul_split(s).zero ? 0.0 : s;
@@ -745,8 +751,11 @@ int build_plan(hoszp_batch* b, const hoszp_field* fields, const uint32_t* blocks
   for (uint64_t i = 0; i < count; ++i) {
     hz::Layout g;
     hz::place(g, fields[i].n, blocks[i], fields[i].eb);
+    const double inv2e = 1.0 / (2.0 * fields[i].eb);
     hf[i] = hz::BatchField{fields[i].d_x, static_cast<uint8_t*>(fields[i].d_out), fields[i].n,
-                           fields[i].eb, 1.0 / (2.0 * fields[i].eb), tiles, blocks[i], 0};
+                           fields[i].eb, inv2e, tiles, blocks[i],
+                           hz::abs_bound_bits(fields[i].eb, inv2e),
+                           hz::abs_bound_bits(fields[i].eb, inv2e, hz::kSmallBin), 0};
     tiles += hz::batch_tiles(g, nt);
     raw += 4 * fields[i].n;
   }

@@ -3,7 +3,9 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <math.h>
 #include <stdint.h>
+#include <string.h>
 
 #include "hoszp.h"
 
@@ -114,6 +116,72 @@ struct Scratch {
 // beyond any wait on running predecessors (tens of microseconds).
 constexpr uint32_t kDefaultWaitLimit = 1u << 24;
 
+// The float inputs whose Eq. 3 bin, floor(((double)x + eb) * inv2e) in
+// binary64 as the kernels evaluate it, lies in [-K, K] (by default the bin
+// range [-(2^31-1), 2^31-1]): the bin is non-decreasing in x, so they form
+// the interval [lo, hi], found by bisection over the ordered float bit
+// patterns.  An empty side is NaN, which every comparison fails.
+inline int32_t float_key(float x) {
+  int32_t b;
+  memcpy(&b, &x, 4);
+  return b >= 0 ? b : (b ^ 0x7fffffff);
+}
+inline float key_float(int32_t k) {
+  const int32_t b = k >= 0 ? k : (k ^ 0x7fffffff);
+  float x;
+  memcpy(&x, &b, 4);
+  return x;
+}
+inline double host_bin(float x, double eb, double inv2e) {
+  const double shifted = double(x) + eb;
+  return floor(shifted * inv2e);
+}
+inline void bin_range_floats(double eb, double inv2e, float& lo, float& hi,
+                             double K = 2147483647.0) {
+  const int32_t kmin = float_key(-3.40282347e+38f), kmax = float_key(3.40282347e+38f);
+  // hi: the largest key whose bin is <= K
+  if (!(host_bin(key_float(kmin), eb, inv2e) <= K)) {
+    hi = NAN;
+  } else if (host_bin(key_float(kmax), eb, inv2e) <= K) {
+    hi = key_float(kmax);
+  } else {
+    int64_t a = kmin, b = kmax;  // bin(a) <= K < bin(b)
+    while (b - a > 1) {
+      const int64_t m = a + (b - a) / 2;
+      if (host_bin(key_float(int32_t(m)), eb, inv2e) <= K) a = m; else b = m;
+    }
+    hi = key_float(int32_t(a));
+  }
+  // lo: the smallest key whose bin is >= -K
+  if (!(host_bin(key_float(kmax), eb, inv2e) >= -K)) {
+    lo = NAN;
+  } else if (host_bin(key_float(kmin), eb, inv2e) >= -K) {
+    lo = key_float(kmin);
+  } else {
+    int64_t a = kmin, b = kmax;  // bin(a) < -K <= bin(b)
+    while (b - a > 1) {
+      const int64_t m = a + (b - a) / 2;
+      if (host_bin(key_float(int32_t(m)), eb, inv2e) >= -K) b = m; else a = m;
+    }
+    lo = key_float(int32_t(b));
+  }
+}
+// Bits of the largest T with [-T, T] inside [lo, hi] for the bound K (0
+// always is: its bin is floor(1/2) = 0), so |x| <= T guarantees |bin| <= K.
+inline uint32_t abs_bound_bits(double eb, double inv2e, double K = 2147483647.0) {
+  float lo, hi;
+  bin_range_floats(eb, inv2e, lo, hi, K);
+  float t = 0.0f;
+  if (lo == lo && hi == hi) t = fmaxf(fminf(-lo, hi), 0.0f);
+  uint32_t b;
+  memcpy(&b, &t, 4);
+  return b;
+}
+
+// Bins below this bound in magnitude let a segment's bin sums be formed in
+// binary64 without rounding (32 squares below 2^42 sum below 2^47).
+constexpr double kSmallBin = 2097151.0;  // 2^21 - 1
+
 // Scalar multiplier, classified on the host (see mul_split()).
 struct MulScalar {
   double s;     // the scalar
@@ -156,6 +224,8 @@ struct BatchField {
   double eb, inv2e;
   uint64_t tile0;   // first work-list tile of the field
   uint32_t block;
+  uint32_t abs_ok;     // abs_bound_bits(eb, inv2e)
+  uint32_t abs_small;  // abs_bound_bits(eb, inv2e, kSmallBin)
   uint32_t pad;
 };
 

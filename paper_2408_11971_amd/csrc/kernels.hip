@@ -493,6 +493,49 @@ __device__ __forceinline__ void pack32(uint32_t* dst, const uint32_t* mag, uint3
   }
 }
 
+// pack32 taking G fields per accumulator step: the G fields of a group are
+// first joined in one 32-bit word (G w <= 32), so the 64-bit shift, the
+// count and the conditional word store run 32 / G times instead of 32.
+template <int G>
+__device__ __forceinline__ void pack32_g(uint32_t* dst, const uint32_t* mag, uint32_t w) {
+  uint64_t acc = 0;
+  uint32_t nbits = 0, o = 0;
+#pragma unroll
+  for (int j = 0; j < 32; j += G) {
+    constexpr int kLast = 32 % G;  // fields of a last, shorter group
+    const int n = (j + G <= 32) ? G : kLast;
+    uint32_t c = mag[j];
+#pragma unroll
+    for (int k = 1; k < G; ++k)
+      if (k < n) c = (c << w) | mag[j + k];
+    const uint32_t cw = uint32_t(n) * w;
+    acc = (acc << cw) | c;
+    nbits += cw;
+    if (nbits >= 32) {
+      nbits -= 32;
+      dst[o++] = uint32_t(acc >> nbits);
+    }
+  }
+}
+
+// Group size for pack32_grouped: the most fields of the widest width in the
+// wave that fit one 32-bit word (wave-uniform; call with every lane active).
+__device__ __forceinline__ uint32_t pack_group(uint32_t w) {
+  const uint32_t wmax = ~wave_min(~w);
+  return uni32(wmax <= 8 ? 4u : wmax <= 10 ? 3u : wmax <= 16 ? 2u : 1u);
+}
+
+// pack32 with a wave-uniform group size from pack_group (w > 0).
+__device__ __forceinline__ void pack32_grouped(uint32_t* dst, const uint32_t* mag, uint32_t w,
+                                               uint32_t group) {
+  switch (group) {
+    case 4: pack32_g<4>(dst, mag, w); break;
+    case 3: pack32_g<3>(dst, mag, w); break;
+    case 2: pack32_g<2>(dst, mag, w); break;
+    default: pack32_g<1>(dst, mag, w); break;
+  }
+}
+
 // Bins of a block stay in range if |O| + (len-1)(2^w - 1) fits.
 __device__ __forceinline__ bool bins_surely_in_range(int64_t outlier, uint64_t blen, uint32_t w) {
   const uint64_t a = uint64_t(outlier < 0 ? -outlier : outlier);
@@ -751,6 +794,7 @@ struct CompressParams {
   uint8_t* out;
   Layout g;
   double eb, inv2e;
+  uint32_t abs_ok;  // abs_bound_bits(eb, inv2e)
   Scratch s;
   hoszp_result* res;
 };
@@ -780,68 +824,94 @@ struct BinSums {
   }
 };
 
-// Quantize 32 values, form Lorenzo deltas, split signs and magnitudes.
-// FULL: all 32 slots valid (no padding checks).  STATS: also add the valid
-// bins to `sums`.
+// Saturating binary64 -> integer conversions (one VALU op each, NaN -> 0):
+// they are only reached with an out-of-range value when the segment's range
+// flag is already down, and their results are then never used.
+__device__ __forceinline__ uint32_t cvt_abs_u32(double d) {
+  uint32_t r;
+  asm("v_cvt_u32_f64 %0, |%1|" : "=v"(r) : "v"(d));
+  return r;
+}
+__device__ __forceinline__ int32_t cvt_i32(double d) {
+  int32_t r;
+  asm("v_cvt_i32_f64 %0, %1" : "=v"(r) : "v"(d));
+  return r;
+}
+
+// Quantize the 32 values of a segment (Eq. 3), form the Lorenzo deltas
+// (Eq. 4; slot 0 of a block's first segment is the outlier) and split them
+// into sign bits (slot j at bit 31 - j) and magnitudes.  FULL: all 32 slots
+// valid.  The deltas are formed in binary64: the bins f_j are integers below
+// 2^31 in magnitude, so d = f_j - f_{j-1} is exact and |d| < 2^32 converts
+// exactly.
+// `prevf` is the bin before the segment (when it does not start its block).
+// Range and finiteness are checked by the caller (abs_max).  STATS: the sum
+// of the valid bins and of their squares in binary64, exact when every bin is
+// below kSmallBin in magnitude (the caller checks that, again with abs_max).
 template <bool FULL, bool STATS>
-__device__ __forceinline__ void quantize_segment(const float* v, uint32_t cnt, bool first_seg,
-                                                 int32_t prev, double eb, double inv2e,
-                                                 uint32_t* mag, uint32_t& sgn, uint32_t& mx,
-                                                 int32_t& outlier, uint32_t& bad, BinSums& sums) {
-  int32_t qp = prev;
-  // STATS: the segment's bins are summed in 32 bits and their squares in 64
-  // (exact while every |bin| < 2^26: 32 of them sum below 2^31 and 2^57), else
-  // the sums are redone one bin at a time from the deltas below
-  int32_t ss = 0, qlo = 0, qhi = 0;
-  uint64_t sq = 0;
+__device__ __forceinline__ void quantize_fast(const float* v, uint32_t cnt, bool first_seg,
+                                              double prevf, double eb, double inv2e,
+                                              uint32_t* mag, uint32_t& sgn, uint32_t& mx,
+                                              int32_t& outlier, double& ssum, double& qsum) {
+  double fp = prevf;
 #pragma unroll
   for (int j = 0; j < 32; ++j) {
-    const float xv = v[j];
-    const double f = bin_real(xv, eb, inv2e);
-    const bool ok = f >= -kBinMaxD && f <= kBinMaxD;
-    const int32_t q = ok ? int32_t(f) : 0;
+    const double f = bin_real(v[j], eb, inv2e);
     const bool valid = FULL || uint32_t(j) < cnt;
-    if (valid && !ok) bad |= isfinite(xv) ? ST_RANGE : ST_NONFINITE;
     if (STATS && valid) {
-      ss += q;
-      sq += uint64_t(int64_t(q) * int64_t(q));
-      qlo = min(qlo, q);
-      qhi = max(qhi, q);
+      ssum += f;
+      qsum = fma(f, f, qsum);
     }
-    bool neg = false;
-    uint32_t m = 0;
-    if (j == 0 && first_seg) {
-      outlier = q;
-    } else {
-      m = delta_mag(q, qp, neg);
+    const double d = f - fp;
+    uint32_t m = cvt_abs_u32(d);
+    bool neg = d < 0.0;
+    if (j == 0) {
+      if (first_seg) {
+        outlier = cvt_i32(f);
+        m = 0;
+        neg = false;
+      }
     }
     if (!valid) {
       m = 0;
       neg = false;
     }
     mag[j] = m;
-    sgn |= uint32_t(neg) << (31 - j);
+    sgn = (sgn << 1) | uint32_t(neg);  // slot j ends at bit 31 - j
     mx = max(mx, m);
-    qp = q;
-  }
-  if (STATS) {
-    constexpr int32_t kSmall = 1 << 26;
-    if (qlo > -kSmall && qhi < kSmall) {
-      sums.add_segment(ss, sq);
-    } else {  // rebuild the bins from the outlier or prev and the deltas
-      int32_t q = prev;
-      for (int j = 0; j < int(cnt); ++j) {
-        if (j == 0 && first_seg) {
-          q = outlier;
-        } else {
-          const uint32_t m = mag[j];
-          q = int32_t(((sgn >> (31 - j)) & 1u) ? uint32_t(q) - m : uint32_t(q) + m);
-        }
-        sums.add(q);
-      }
-    }
+    fp = f;
+    // one slot at a time: hoisting the independent binary64 chains of later
+    // slots only lengthens live ranges (the other waves hide the latency)
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
+
+// Largest |x| bit pattern over the valid values of a segment, for the range
+// tests before quantize_fast: am <= abs_bound_bits(eb, inv2e, K) guarantees
+// every bin is within [-K, K]; NaN and infinity have larger bits than any
+// finite bound.  Computed before the quantization loop, so the compiler
+// cannot sink the tests past it (which would keep every slot's binary64 bin
+// live).
+template <bool FULL>
+__device__ __forceinline__ uint32_t abs_max(const float* v, uint32_t cnt) {
+  uint32_t am = 0;
+#pragma unroll
+  for (int j = 0; j < 32; ++j)
+    if (FULL || uint32_t(j) < cnt) am = max(am, __float_as_uint(v[j]) & 0x7fffffffu);
+  return am;
+}
+
+// Error bits of a segment whose quantize_fast failed (reads it again).
+__device__ __noinline__ uint32_t segment_errors(const float* xs, uint32_t cnt, double eb,
+                                                double inv2e) {
+  uint32_t bad = 0;
+  for (uint32_t j = 0; j < cnt; ++j) {
+    const float xv = xs[j];
+    if (!(fabs(bin_real(xv, eb, inv2e)) <= kBinMaxD)) bad |= isfinite(xv) ? ST_RANGE : ST_NONFINITE;
+  }
+  return bad;
+}
+
 
 // LDS of one compress workgroup.
 template <int NT = kThreads>
@@ -864,7 +934,7 @@ struct CompressShared {
 // barriers.
 template <int SPB, bool STATS, int NT = kThreads>
 __device__ __forceinline__ uint64_t compress_tile(const float* x, uint8_t* out, const Layout& g, double eb,
-                                  double inv2e, uint64_t tile, uint64_t* st, uint32_t epoch,
+                                  double inv2e, uint32_t abs_ok, uint32_t abs_small, uint64_t tile, uint64_t* st, uint32_t epoch,
                                   uint32_t limit, CompressShared<NT>& sh, uint32_t& bad, BinSums& sums,
                                   uint32_t* ticket, uint32_t& next) {
   constexpr uint32_t L = SPB * 32;
@@ -882,12 +952,12 @@ __device__ __forceinline__ uint64_t compress_tile(const float* x, uint8_t* out, 
   uint32_t sgn = 0, mx = 0;
   int32_t outlier = 0;
   if (cnt > 0) {
-    int32_t prev = 0;
-    if (sub > 0) {  // the slot before this segment belongs to the same block
-      const double f = bin_real(x[first - 1], eb, inv2e);
-      prev = (f >= -kBinMaxD && f <= kBinMaxD) ? int32_t(f) : 0;
-    }
+    // the bin of the slot before this segment, when it is in the same block
+    // (an out-of-range one is that slot's own segment's error)
+    const double prevf = sub > 0 ? bin_real(x[first - 1], eb, inv2e) : 0.0;
     float v[32];
+    uint32_t am;
+    double ssum = 0.0, qsum = 0.0;
     if (cnt == 32) {
       const float4* src = reinterpret_cast<const float4*>(x + first);
 #pragma unroll
@@ -898,13 +968,33 @@ __device__ __forceinline__ uint64_t compress_tile(const float* x, uint8_t* out, 
         v[4 * k + 2] = t.z;
         v[4 * k + 3] = t.w;
       }
-      quantize_segment<true, STATS>(v, cnt, sub == 0, prev, eb, inv2e, mag, sgn, mx, outlier,
-                                    bad, sums);
+      am = abs_max<true>(v, cnt);
+      if (am > abs_ok) bad |= segment_errors(x + first, cnt, eb, inv2e);
+      quantize_fast<true, STATS>(v, cnt, sub == 0, prevf, eb, inv2e, mag, sgn, mx, outlier, ssum,
+                                 qsum);
     } else {
 #pragma unroll
       for (int j = 0; j < 32; ++j) v[j] = uint32_t(j) < cnt ? x[first + j] : 0.0f;
-      quantize_segment<false, STATS>(v, cnt, sub == 0, prev, eb, inv2e, mag, sgn, mx, outlier,
-                                     bad, sums);
+      am = abs_max<false>(v, cnt);
+      if (am > abs_ok) bad |= segment_errors(x + first, cnt, eb, inv2e);
+      quantize_fast<false, STATS>(v, cnt, sub == 0, prevf, eb, inv2e, mag, sgn, mx, outlier, ssum,
+                                  qsum);
+    }
+    if (STATS) {
+      if (am <= abs_small) {
+        sums.add_segment(int32_t(ssum), uint64_t(qsum));
+      } else {  // wide bins: rebuild them from the outlier or prev and the deltas
+        int32_t q = sub > 0 ? cvt_i32(prevf) : 0;
+        for (int j = 0; j < int(cnt); ++j) {
+          if (j == 0 && sub == 0) {
+            q = outlier;
+          } else {
+            const uint32_t m = mag[j];
+            q = int32_t(((sgn >> (31 - j)) & 1u) ? uint32_t(q) - m : uint32_t(q) + m);
+          }
+          sums.add(q);
+        }
+      }
     }
   } else {
 #pragma unroll
@@ -919,7 +1009,8 @@ __device__ __forceinline__ uint64_t compress_tile(const float* x, uint8_t* out, 
   // that does not need the tile's offset (packing into LDS, the width,
   // outlier and sign sections) before waiting on the predecessors.
   lb_publish(st, tile, tile_words, epoch);
-  if (w > 0) pack32(&sh.pay[off], mag, w);
+  const uint32_t group = pack_group(w);
+  if (w > 0) pack32_grouped(&sh.pay[off], mag, w, group);
   if (active) {
     if (sub == 0) {
       out[g.off_w + blk] = uint8_t(w);
@@ -955,7 +1046,7 @@ __global__ void __launch_bounds__(NT) k_compress(CompressParams p) {
     const uint64_t tile = uni64(sh.ticket);
     if (tile >= ntiles) break;
     const uint64_t words =
-        compress_tile<SPB, false, NT>(p.x, p.out, g, p.eb, p.inv2e, tile, p.s.st_out, epoch,
+        compress_tile<SPB, false, NT>(p.x, p.out, g, p.eb, p.inv2e, p.abs_ok, 0u, tile, p.s.st_out, epoch,
                                       p.s.wait_limit, sh,
                                   bad, none, &p.s.ctrl[C_TICKET], next);
     if (tid == 0 && tile == ntiles - 1) st_dev(&p.s.acc[A_OUT], g.off_p + 4 * words);
@@ -1084,15 +1175,15 @@ k_batch(BatchParams p) {
     uint64_t words = 0;
     switch (g.spb) {
       case 1:
-        words = compress_tile<1, true, NT>(fd.x, fd.out, g, fd.eb, fd.inv2e, tile, p.st + fd.tile0,
+        words = compress_tile<1, true, NT>(fd.x, fd.out, g, fd.eb, fd.inv2e, fd.abs_ok, fd.abs_small, tile, p.st + fd.tile0,
                                        epoch, p.wait_limit, sh, bad, sums, &p.ctrl[B_TICKET], next);
         break;
       case 2:
-        words = compress_tile<2, true, NT>(fd.x, fd.out, g, fd.eb, fd.inv2e, tile, p.st + fd.tile0,
+        words = compress_tile<2, true, NT>(fd.x, fd.out, g, fd.eb, fd.inv2e, fd.abs_ok, fd.abs_small, tile, p.st + fd.tile0,
                                        epoch, p.wait_limit, sh, bad, sums, &p.ctrl[B_TICKET], next);
         break;
       default:  // 4: batches take blocks up to 128 (checked when planned)
-        words = compress_tile<4, true, NT>(fd.x, fd.out, g, fd.eb, fd.inv2e, tile, p.st + fd.tile0,
+        words = compress_tile<4, true, NT>(fd.x, fd.out, g, fd.eb, fd.inv2e, fd.abs_ok, fd.abs_small, tile, p.st + fd.tile0,
                                        epoch, p.wait_limit, sh, bad, sums, &p.ctrl[B_TICKET], next);
         break;
     }
@@ -2583,7 +2674,7 @@ static hipError_t launch_widths(const Scratch& s, const Grids& gr, int which, co
 
 hipError_t launch_compress(const Scratch& s, const Grids& gr, const float* x, const Layout& g,
                            double inv2e, uint8_t* out, hoszp_result* res, hipStream_t st) {
-  CompressParams p{x, out, g, g.eb, inv2e, s, res};
+  CompressParams p{x, out, g, g.eb, inv2e, abs_bound_bits(g.eb, inv2e), s, res};
   const uint64_t ntiles = (g.nseg + kCompressThreads - 1) / kCompressThreads;
   const uint64_t grid = ntiles < uint64_t(gr.compress) ? ntiles : uint64_t(gr.compress);
   switch (g.L) {

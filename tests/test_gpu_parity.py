@@ -389,3 +389,69 @@ def test_mul_exact_rounding_classes(dev):
         assert np.array_equal(got, ref.mul(xc, s)), f"mul stream differs for s={s!r}"
         assert np.array_equal(ref.decode_bins(got).astype(np.int64),
                               np.array(want, dtype=np.int64)), f"mul bins differ for s={s!r}"
+
+
+def wave_width_field(L, seed):
+    """Float field whose waves (64 consecutive segments of 32 slots) have
+    widest block widths 1, 2, ..., 23 in turn (twice over), the other
+    blocks of each wave narrower.  Slots alternate between a block base and
+    base + m_j, so every delta is +-m_j and a block's width is the bit length
+    of its largest m_j; all bins stay below 2^24 in magnitude, so with
+    eps = 1/2 each value is its own (exact) bin."""
+    rng = np.random.default_rng(seed)
+    blocks_per_wave = 64 // (L // 32)
+    out = []
+    for wave in range(2 * 23):
+        W = 1 + wave % 23
+        for b in range(blocks_per_wave):
+            wb = W if b == (wave * 7) % blocks_per_wave else int(rng.integers(0, W + 1))
+            m = rng.integers(0, 1 << wb, L)
+            m[int(rng.integers(1, L))] = (1 << wb) - 1
+            base = int(rng.integers(-(1 << 22), 1 << 22))
+            q = base + np.where(np.arange(L) % 2 == 1, m, 0)
+            out.append(q)
+    q = np.concatenate(out)
+    x = q.astype(np.float32)
+    assert np.array_equal(x.astype(np.int64), q)
+    return x
+
+
+def wave_max_widths(c, L):
+    """Widest block width of every wave of a stream (oracle stream)."""
+    nb = ref.info(c)["n"] // L
+    w = c[64:64 + nb].astype(np.int64)
+    per = 64 // (L // 32)
+    return [int(w[k:k + per].max()) for k in range(0, nb, per)]
+
+
+@pytest.mark.parametrize("L", BLOCKS)
+def test_every_wave_max_width(dev, L):
+    """Encoders pack 1 to 4 fields per step depending on the widest width in
+    a wave (64 segments); this field gives every wave-widest width 1..23, so
+    every step size and every last, shorter group is exercised."""
+    x = wave_width_field(L, 100 + L)
+    xc = ref.compress(x, 0.5, L)
+    assert wave_max_widths(xc, L) == [1 + k % 23 for k in range(2 * 23)]
+    print(f"case wave widths L={L} n={x.size}", flush=True)
+    check_all_ops(x, x[::-1].copy(), 0.5, L, dev, scalars=(1.0, -0.5))
+
+
+@pytest.mark.parametrize("eb", [1e-3, 0.5, 7.3e-6])
+def test_range_interval_ends(dev, eb):
+    """Inputs at both ends of the accepted interval (bins +-(2^31-1) or the
+    nearest) compress exactly like the oracle; the next float beyond either
+    end is RANGE.  The kernels test ranges against a bound derived from this
+    interval, so its ends are where a mistake would show."""
+    lo, hi = hz.bin_range(eb)
+    x = gaussian(70000, 3, scale=100 * eb)
+    for k, pos in enumerate((5, 40, 31, 32, 33, 1023, 32768, 65535, 69999)):
+        x[pos] = hi if k % 2 == 0 else lo
+    print(f"case range ends eb={eb} lo={lo} hi={hi}", flush=True)
+    for L in BLOCKS:
+        xc = ref.compress(x, eb, L)
+        assert np.array_equal(host(hz.compress(gpu(x, dev), eb, L)), xc), L
+    for beyond in (np.nextafter(np.float32(hi), np.float32(np.inf)),
+                   np.nextafter(np.float32(lo), np.float32(-np.inf))):
+        y = x.copy()
+        y[40000] = beyond
+        assert err_of(hz.compress, gpu(y, dev), eb, 32) == hz.ERR_RANGE
