@@ -754,8 +754,8 @@ int build_plan(hoszp_batch* b, const hoszp_field* fields, const uint32_t* blocks
     const double inv2e = 1.0 / (2.0 * fields[i].eb);
     hf[i] = hz::BatchField{fields[i].d_x, static_cast<uint8_t*>(fields[i].d_out), fields[i].n,
                            fields[i].eb, inv2e, tiles, blocks[i],
-                           hz::abs_bound_bits(fields[i].eb, inv2e),
-                           hz::abs_bound_bits(fields[i].eb, inv2e, hz::kSmallBin), 0};
+                           hz::abs_bound(fields[i].eb, inv2e),
+                           hz::abs_bound(fields[i].eb, inv2e, hz::kSmallBin), 0};
     tiles += hz::batch_tiles(g, nt);
     raw += 4 * fields[i].n;
   }

@@ -166,16 +166,12 @@ inline void bin_range_floats(double eb, double inv2e, float& lo, float& hi,
     lo = key_float(int32_t(b));
   }
 }
-// Bits of the largest T with [-T, T] inside [lo, hi] for the bound K (0
-// always is: its bin is floor(1/2) = 0), so |x| <= T guarantees |bin| <= K.
-inline uint32_t abs_bound_bits(double eb, double inv2e, double K = 2147483647.0) {
+// The largest T with [-T, T] inside [lo, hi] for the bound K (0 always is:
+// its bin is floor(1/2) = 0), so |x| <= T guarantees |bin| <= K.
+inline float abs_bound(double eb, double inv2e, double K = 2147483647.0) {
   float lo, hi;
   bin_range_floats(eb, inv2e, lo, hi, K);
-  float t = 0.0f;
-  if (lo == lo && hi == hi) t = fmaxf(fminf(-lo, hi), 0.0f);
-  uint32_t b;
-  memcpy(&b, &t, 4);
-  return b;
+  return (lo == lo && hi == hi) ? fmaxf(fminf(-lo, hi), 0.0f) : 0.0f;
 }
 
 // Bins below this bound in magnitude let a segment's bin sums be formed in
@@ -224,8 +220,8 @@ struct BatchField {
   double eb, inv2e;
   uint64_t tile0;   // first work-list tile of the field
   uint32_t block;
-  uint32_t abs_ok;     // abs_bound_bits(eb, inv2e)
-  uint32_t abs_small;  // abs_bound_bits(eb, inv2e, kSmallBin)
+  float abs_ok;     // abs_bound(eb, inv2e)
+  float abs_small;  // abs_bound(eb, inv2e, kSmallBin)
   uint32_t pad;
 };
 

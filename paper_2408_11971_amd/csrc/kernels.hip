@@ -794,7 +794,7 @@ struct CompressParams {
   uint8_t* out;
   Layout g;
   double eb, inv2e;
-  uint32_t abs_ok;  // abs_bound_bits(eb, inv2e)
+  float abs_ok;  // abs_bound(eb, inv2e)
   Scratch s;
   hoszp_result* res;
 };
@@ -845,9 +845,9 @@ __device__ __forceinline__ int32_t cvt_i32(double d) {
 // 2^31 in magnitude, so d = f_j - f_{j-1} is exact and |d| < 2^32 converts
 // exactly.
 // `prevf` is the bin before the segment (when it does not start its block).
-// Range and finiteness are checked by the caller (abs_max).  STATS: the sum
+// Range and finiteness are checked by the caller (abs_sum).  STATS: the sum
 // of the valid bins and of their squares in binary64, exact when every bin is
-// below kSmallBin in magnitude (the caller checks that, again with abs_max).
+// below kSmallBin in magnitude (the caller checks that, again with abs_sum).
 template <bool FULL, bool STATS>
 __device__ __forceinline__ void quantize_fast(const float* v, uint32_t cnt, bool first_seg,
                                               double prevf, double eb, double inv2e,
@@ -862,22 +862,24 @@ __device__ __forceinline__ void quantize_fast(const float* v, uint32_t cnt, bool
       ssum += f;
       qsum = fma(f, f, qsum);
     }
+    // d is +0 when f = fp, so its sign bit is the delta's sign
     const double d = f - fp;
     uint32_t m = cvt_abs_u32(d);
-    bool neg = d < 0.0;
+    uint32_t hi = uint32_t(__double2hiint(d));
     if (j == 0) {
       if (first_seg) {
         outlier = cvt_i32(f);
         m = 0;
-        neg = false;
+        hi = 0;
       }
     }
     if (!valid) {
       m = 0;
-      neg = false;
+      hi = 0;
     }
     mag[j] = m;
-    sgn = (sgn << 1) | uint32_t(neg);  // slot j ends at bit 31 - j
+    // (sgn << 1) | sign bit of d: slot j ends at bit 31 - j
+    sgn = __builtin_amdgcn_alignbit(sgn, hi, 31);
     mx = max(mx, m);
     fp = f;
     // one slot at a time: hoisting the independent binary64 chains of later
@@ -886,19 +888,20 @@ __device__ __forceinline__ void quantize_fast(const float* v, uint32_t cnt, bool
   }
 }
 
-// Largest |x| bit pattern over the valid values of a segment, for the range
-// tests before quantize_fast: am <= abs_bound_bits(eb, inv2e, K) guarantees
-// every bin is within [-K, K]; NaN and infinity have larger bits than any
-// finite bound.  Computed before the quantization loop, so the compiler
+// Sum of |x| over the valid values of a segment, for the range tests before
+// quantize_fast: a rounded sum of non-negative terms is at least each term,
+// so sum <= abs_bound(eb, inv2e, K) guarantees every bin is within [-K, K];
+// NaN, infinity and overflow fail every such test (the exact classification
+// then decides).  Computed before the quantization loop, so the compiler
 // cannot sink the tests past it (which would keep every slot's binary64 bin
 // live).
 template <bool FULL>
-__device__ __forceinline__ uint32_t abs_max(const float* v, uint32_t cnt) {
-  uint32_t am = 0;
+__device__ __forceinline__ float abs_sum(const float* v, uint32_t cnt) {
+  float a = 0.0f;
 #pragma unroll
   for (int j = 0; j < 32; ++j)
-    if (FULL || uint32_t(j) < cnt) am = max(am, __float_as_uint(v[j]) & 0x7fffffffu);
-  return am;
+    if (FULL || uint32_t(j) < cnt) a += fabsf(v[j]);
+  return a;
 }
 
 // Error bits of a segment whose quantize_fast failed (reads it again).
@@ -934,7 +937,7 @@ struct CompressShared {
 // barriers.
 template <int SPB, bool STATS, int NT = kThreads>
 __device__ __forceinline__ uint64_t compress_tile(const float* x, uint8_t* out, const Layout& g, double eb,
-                                  double inv2e, uint32_t abs_ok, uint32_t abs_small, uint64_t tile, uint64_t* st, uint32_t epoch,
+                                  double inv2e, float abs_ok, float abs_small, uint64_t tile, uint64_t* st, uint32_t epoch,
                                   uint32_t limit, CompressShared<NT>& sh, uint32_t& bad, BinSums& sums,
                                   uint32_t* ticket, uint32_t& next) {
   constexpr uint32_t L = SPB * 32;
@@ -956,7 +959,7 @@ __device__ __forceinline__ uint64_t compress_tile(const float* x, uint8_t* out, 
     // (an out-of-range one is that slot's own segment's error)
     const double prevf = sub > 0 ? bin_real(x[first - 1], eb, inv2e) : 0.0;
     float v[32];
-    uint32_t am;
+    float am;
     double ssum = 0.0, qsum = 0.0;
     if (cnt == 32) {
       const float4* src = reinterpret_cast<const float4*>(x + first);
@@ -968,15 +971,15 @@ __device__ __forceinline__ uint64_t compress_tile(const float* x, uint8_t* out, 
         v[4 * k + 2] = t.z;
         v[4 * k + 3] = t.w;
       }
-      am = abs_max<true>(v, cnt);
-      if (am > abs_ok) bad |= segment_errors(x + first, cnt, eb, inv2e);
+      am = abs_sum<true>(v, cnt);
+      if (!(am <= abs_ok)) bad |= segment_errors(x + first, cnt, eb, inv2e);
       quantize_fast<true, STATS>(v, cnt, sub == 0, prevf, eb, inv2e, mag, sgn, mx, outlier, ssum,
                                  qsum);
     } else {
 #pragma unroll
       for (int j = 0; j < 32; ++j) v[j] = uint32_t(j) < cnt ? x[first + j] : 0.0f;
-      am = abs_max<false>(v, cnt);
-      if (am > abs_ok) bad |= segment_errors(x + first, cnt, eb, inv2e);
+      am = abs_sum<false>(v, cnt);
+      if (!(am <= abs_ok)) bad |= segment_errors(x + first, cnt, eb, inv2e);
       quantize_fast<false, STATS>(v, cnt, sub == 0, prevf, eb, inv2e, mag, sgn, mx, outlier, ssum,
                                   qsum);
     }
@@ -1046,7 +1049,7 @@ __global__ void __launch_bounds__(NT) k_compress(CompressParams p) {
     const uint64_t tile = uni64(sh.ticket);
     if (tile >= ntiles) break;
     const uint64_t words =
-        compress_tile<SPB, false, NT>(p.x, p.out, g, p.eb, p.inv2e, p.abs_ok, 0u, tile, p.s.st_out, epoch,
+        compress_tile<SPB, false, NT>(p.x, p.out, g, p.eb, p.inv2e, p.abs_ok, 0.0f, tile, p.s.st_out, epoch,
                                       p.s.wait_limit, sh,
                                   bad, none, &p.s.ctrl[C_TICKET], next);
     if (tid == 0 && tile == ntiles - 1) st_dev(&p.s.acc[A_OUT], g.off_p + 4 * words);
@@ -2674,7 +2677,7 @@ static hipError_t launch_widths(const Scratch& s, const Grids& gr, int which, co
 
 hipError_t launch_compress(const Scratch& s, const Grids& gr, const float* x, const Layout& g,
                            double inv2e, uint8_t* out, hoszp_result* res, hipStream_t st) {
-  CompressParams p{x, out, g, g.eb, inv2e, abs_bound_bits(g.eb, inv2e), s, res};
+  CompressParams p{x, out, g, g.eb, inv2e, abs_bound(g.eb, inv2e), s, res};
   const uint64_t ntiles = (g.nseg + kCompressThreads - 1) / kCompressThreads;
   const uint64_t grid = ntiles < uint64_t(gr.compress) ? ntiles : uint64_t(gr.compress);
   switch (g.L) {
