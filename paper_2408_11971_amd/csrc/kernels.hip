@@ -2039,7 +2039,8 @@ __global__ void __launch_bounds__(NT) k_add(AddParams p) {
     const uint32_t off_z = wg_scan<NT>(w, tw_z, s_tmp);  // barriers: all threads done reading B
     // publish the output tile's size, then pack and store what needs no offset
     lb_publish(p.s.st_out, tile, tw_z, epoch);
-    if (w > 0) pack32(&s_pay[off_z], mag, w);
+    const uint32_t group = pack_group(w);
+    if (w > 0) pack32_grouped(&s_pay[off_z], mag, w, group);
     if (active) {
       if (sub == 0) {
         p.out[g.off_w + blk] = uint8_t(w);
@@ -2502,7 +2503,8 @@ __global__ void __launch_bounds__(NT) k_bivar(BivarParams p) {
     uint32_t tw_z;
     const uint32_t off_z = wg_scan<NT>(wz, tw_z, s_tmp);  // barriers: all threads done reading B
     lb_publish(p.s.st_out, tile, tw_z, epoch);
-    if (wz > 0) pack32(&s_pay[off_z], mag, wz);
+    const uint32_t group = pack_group(wz);
+    if (wz > 0) pack32_grouped(&s_pay[off_z], mag, wz, group);
     if (active) {
       if (sub == 0) {
         p.out[g.off_w + blk] = uint8_t(wz);
