@@ -2087,30 +2087,40 @@ __device__ __forceinline__ int32_t scaled_bin(int32_t q, double s, uint32_t& bad
 
 // Scale a segment's bins front to back and turn each at once into its output
 // delta's magnitude and sign, so an input bin dies as its delta is made.
-// Slot 0's delta needs the previous segment's last scaled bin: its scaled bin
-// is returned in z0 and its magnitude left for the caller.  FULL: every lane
-// of the wave holds 32 valid slots, so no slot needs a bounds test.
+// The scaled bins z_j = mul_round(s, q_j) are integers, so the delta
+// z_j - z_{j-1} is exact in binary64 while both are bins (|z| <= 2^31 - 1),
+// and one conversion of its absolute value and one funnel shift of its sign
+// bit give the magnitude and the sign word (slot j at bit 31 - j; slot 0's
+// bit is left 0).  The range test is a running maximum of |z_j|.  Slot 0's
+// delta needs the previous segment's last scaled bin: its scaled bin is
+// returned in z0 and its magnitude left for the caller.  FULL: every lane of
+// the wave holds 32 valid slots, so no slot needs a bounds test.
 template <bool FULL>
 __device__ __forceinline__ void scale_deltas(const int32_t* r, uint32_t c32, uint32_t cnt, double s,
                                              uint32_t* mag, uint32_t& sgn, uint32_t& mx,
                                              int32_t& z0, int32_t& zl, uint32_t& bad) {
-  z0 = (FULL || cnt > 0) ? scaled_bin(int32_t(c32 + uint32_t(r[0])), s, bad) : 0;
-  int32_t zp = z0;
+  double zp = (FULL || cnt > 0) ? mul_round(s, double(int32_t(c32 + uint32_t(r[0])))) : 0.0;
+  double zmax = fabs(zp);
+  z0 = cvt_i32(zp);
   mag[0] = 0;
 #pragma unroll
   for (int j = 1; j < 32; ++j) {
-    uint32_t m = 0;
-    bool neg = false;
+    uint32_t m = 0, hi = 0;
     if (FULL || uint32_t(j) < cnt) {
-      const int32_t z = scaled_bin(int32_t(c32 + uint32_t(r[j])), s, bad);
-      m = delta_mag(z, zp, neg);
+      const double z = mul_round(s, double(int32_t(c32 + uint32_t(r[j]))));
+      const double d = z - zp;
+      m = cvt_abs_u32(d);
+      hi = uint32_t(__double2hiint(d));  // d is +0 when z = zp
+      zmax = fmax(zmax, fabs(z));
       zp = z;
     }
     mag[j] = m;
-    sgn |= uint32_t(neg) << (31 - j);
+    sgn = __builtin_amdgcn_alignbit(sgn, hi, 31);
     mx = max(mx, m);
+    __builtin_amdgcn_sched_barrier(0);  // one slot at a time (live ranges)
   }
-  zl = zp;
+  if (!(zmax <= kBinMaxD)) bad |= ST_RANGE;
+  zl = cvt_i32(zp);
 }
 
 // Scalar multiplication, one tile of NT segments per workgroup: decode the
