@@ -2377,6 +2377,8 @@ __global__ void __launch_bounds__(NT) k_bivar(BivarParams p) {
   const uint32_t ex = uint32_t(eb_bits >> 52) & 0x7ffu;
   const uint64_t M = (eb_bits & ((uint64_t(1) << 52) - 1)) | (ex ? uint64_t(1) << 52 : 0u);
   const int sh = ex ? 1075 - int(ex) : 1074;
+  const double two_eps = 2.0 * g.eb;
+  const bool fast_products = two_eps >= 0x1p-900;
   const uint32_t* Sa = reinterpret_cast<const uint32_t*>(p.a + g.off_s);
   const uint32_t* Sb = reinterpret_cast<const uint32_t*>(p.b + gb.off_s);
   const int32_t* Oa = reinterpret_cast<const int32_t*>(p.a + g.off_o);
@@ -2470,27 +2472,70 @@ __global__ void __launch_bounds__(NT) k_bivar(BivarParams p) {
       __syncthreads();  // every lane is done reading B before the next tile stages
       continue;
     }
-    // Hadamard: product bins, their deltas, re-encode
+    // Hadamard: product bins, their deltas, re-encode.  Fast path: while
+    // |q_A q_B| < 2^53 the binary64 product P is exact and the bin is
+    // mul_round(2 eps, P) (2 eps is exact in binary64; 2 eps >= 2^-900
+    // keeps the rounding's error term out of the subnormal range), and the
+    // output deltas come from the binary64 bins as in scalar multiplication;
+    // fl(P) < 2^53 certifies |P| < 2^53, else the segment is redone on the
+    // exact 128-bit path.
     uint32_t mag[32];
     uint32_t sgn = 0, mx = 0;
     int32_t z0 = 0, zp = 0;
+    bool exact_path = !fast_products;
+    if (fast_products) {
+      double zpd = 0.0, zmax = 0.0, pmax = 0.0;
 #pragma unroll
-    for (int j = 0; j < 32; ++j) {
-      uint32_t m = 0;
-      if (uint32_t(j) < cnt) {
-        const int32_t qa = int32_t(ca + uint32_t(ra[j])), qb = int32_t(cb + uint32_t(rb[j]));
-        const int32_t z = product_bin(int64_t(qa) * int64_t(qb), M, sh, bad);
-        if (j == 0) {
-          z0 = z;
-        } else {
-          bool neg = false;
-          m = delta_mag(z, zp, neg);
-          sgn |= uint32_t(neg) << (31 - j);
+      for (int j = 0; j < 32; ++j) {
+        uint32_t m = 0, hi = 0;
+        if (uint32_t(j) < cnt) {
+          const int32_t qa = int32_t(ca + uint32_t(ra[j])), qb = int32_t(cb + uint32_t(rb[j]));
+          const double P = double(qa) * double(qb);
+          pmax = fmax(pmax, fabs(P));
+          const double z = mul_round(two_eps, P);
+          zmax = fmax(zmax, fabs(z));
+          if (j == 0) {
+            z0 = cvt_i32(z);
+          } else {
+            const double d = z - zpd;  // +0 when equal
+            m = cvt_abs_u32(d);
+            hi = uint32_t(__double2hiint(d));
+          }
+          zpd = z;
         }
-        zp = z;
+        mag[j] = m;
+        sgn = __builtin_amdgcn_alignbit(sgn, hi, 31);  // slot j at bit 31 - j
+        mx = max(mx, m);
+        __builtin_amdgcn_sched_barrier(0);  // one slot at a time (live ranges)
       }
-      mag[j] = m;
-      mx = max(mx, m);
+      zp = cvt_i32(zpd);
+      if (!(pmax < 9007199254740992.0)) {
+        exact_path = true;
+        sgn = 0;
+        mx = 0;
+      } else if (!(zmax <= kBinMaxD)) {
+        bad |= ST_RANGE;
+      }
+    }
+    if (exact_path) {
+#pragma unroll
+      for (int j = 0; j < 32; ++j) {
+        uint32_t m = 0;
+        if (uint32_t(j) < cnt) {
+          const int32_t qa = int32_t(ca + uint32_t(ra[j])), qb = int32_t(cb + uint32_t(rb[j]));
+          const int32_t z = product_bin(int64_t(qa) * int64_t(qb), M, sh, bad);
+          if (j == 0) {
+            z0 = z;
+          } else {
+            bool neg = false;
+            m = delta_mag(z, zp, neg);
+            sgn |= uint32_t(neg) << (31 - j);
+          }
+          zp = z;
+        }
+        mag[j] = m;
+        mx = max(mx, m);
+      }
     }
     // slot 0's delta needs the last product bin of the previous segment of
     // the same block (a segment with valid slots after the first always

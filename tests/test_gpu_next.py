@@ -216,6 +216,27 @@ def test_hadamard_exact_cases(dev):
         assert err_of(hz.hadamard, a, gpu(other, dev)) == hz.ERR_MISMATCH
 
 
+def test_hadamard_wide_products(dev):
+    """Products q_A q_B of 2^53 and more with in-range bins (eps = 2^-30:
+    bins up to 2^27, products up to 2^54), exact ties 2 eps P = odd / 2 among
+    them, and eps whose 2 eps is not a power of two: every segment must match
+    the oracle, whichever binary64 or 128-bit path the kernel takes."""
+    rng = np.random.default_rng(16)
+    n = 70001
+    for eb in (2.0**-30, 3 * 2.0**-33):
+        qa = rng.integers(-(1 << 27), (1 << 27) + 1, n).astype(np.int32)
+        qb = rng.integers(-(1 << 27), (1 << 27) + 1, n).astype(np.int32)
+        qa[:3000] = rng.integers(-(1 << 13), (1 << 13) + 1, 3000)      # small products
+        qb[:3000] = rng.integers(-(1 << 13), (1 << 13) + 1, 3000)
+        qa[5000:6000] = 1 << 14                                         # P = 2^28 * odd: ties
+        qb[5000:6000] = ((rng.integers(0, 1 << 12, 1000) * 2 + 1) << 14) * rng.choice([-1, 1], 1000)
+        for L in (32, 128):
+            ac, bc = ref.encode_bins(qa, eb, L), ref.encode_bins(qb, eb, L)
+            print(f"case hadamard wide eb={eb} L={L}", flush=True)
+            want = ref.hadamard(ac, bc)
+            assert np.array_equal(host(hz.hadamard(gpu(ac, dev), gpu(bc, dev))), want), (eb, L)
+
+
 @pytest.mark.parametrize("n,L", PAIR_CASES)
 def test_covariance(dev, n, L):
     print(f"case covariance n={n} L={L}", flush=True)
