@@ -249,7 +249,23 @@ inline __host__ __device__ uint64_t batch_tiles(const Layout& g, uint32_t nt) {
 // Occupancy-derived persistent grid sizes, filled at context creation.
 struct Grids {
   int compress, decode, reduce, add, mul, negate, widths, f32, bivar;
+  int cus;  // compute units of the device
 };
+
+// Segments per compress tile for a field of nseg segments: kSmallTileSegs
+// when even those tiles are no more than the compute units (a field of at
+// most ~2 M values on MI355X: the 1024-segment tiles would leave most CUs
+// idle), else 1024 (one workgroup per CU).  Small tiles are not used for
+// larger fields: with several small tiles per CU all starting at once, every
+// look-back scans far back before any inclusive prefix exists (measured 2x
+// slower on a 6.5 M-value field).  Launches and the status words they use
+// (the allocation-free entry point clears them) both follow this.
+constexpr int kSmallTileSegs = 256;
+inline uint32_t compress_tile_segs(uint64_t nseg, int cus) {
+  return (nseg + kSmallTileSegs - 1) / kSmallTileSegs <= uint64_t(cus > 0 ? cus : 1)
+             ? uint32_t(kSmallTileSegs)
+             : uint32_t(kCompressTileSegs);
+}
 
 // ---- launchers (kernels.hip) ----------------------------------------------
 // Clears the context counters and a result record; only needed after a

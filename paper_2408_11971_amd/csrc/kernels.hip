@@ -1034,7 +1034,8 @@ __device__ __forceinline__ uint64_t compress_tile(const float* x, uint8_t* out, 
 }
 
 template <int SPB, int NT>
-__global__ void __launch_bounds__(NT) k_compress(CompressParams p) {
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
+k_compress(CompressParams p) {
   __shared__ CompressShared<NT> sh;
   const int tid = threadIdx.x;
   const Layout& g = p.g;
@@ -2735,14 +2736,27 @@ static hipError_t launch_widths(const Scratch& s, const Grids& gr, int which, co
 hipError_t launch_compress(const Scratch& s, const Grids& gr, const float* x, const Layout& g,
                            double inv2e, uint8_t* out, hoszp_result* res, hipStream_t st) {
   CompressParams p{x, out, g, g.eb, inv2e, abs_bound(g.eb, inv2e), s, res};
-  const uint64_t ntiles = (g.nseg + kCompressThreads - 1) / kCompressThreads;
-  const uint64_t grid = ntiles < uint64_t(gr.compress) ? ntiles : uint64_t(gr.compress);
-  switch (g.L) {
-    case 32: hipLaunchKernelGGL((k_compress<1, kCompressThreads>), dim3(uint32_t(grid)), dim3(kCompressThreads), 0, st, p); break;
-    case 64: hipLaunchKernelGGL((k_compress<2, kCompressThreads>), dim3(uint32_t(grid)), dim3(kCompressThreads), 0, st, p); break;
-    case 128: hipLaunchKernelGGL((k_compress<4, kCompressThreads>), dim3(uint32_t(grid)), dim3(kCompressThreads), 0, st, p); break;
-    case 256: hipLaunchKernelGGL((k_compress<8, kCompressThreads>), dim3(uint32_t(grid)), dim3(kCompressThreads), 0, st, p); break;
-    default: return hipErrorInvalidValue;
+  const uint32_t nt = compress_tile_segs(g.nseg, gr.cus);
+  const uint64_t ntiles = (g.nseg + nt - 1) / nt;
+  if (nt == uint32_t(kCompressThreads)) {
+    const uint64_t grid = ntiles < uint64_t(gr.compress) ? ntiles : uint64_t(gr.compress);
+    const dim3 gd = dim3(uint32_t(grid)), bd = dim3(kCompressThreads);
+    switch (g.L) {
+      case 32: hipLaunchKernelGGL((k_compress<1, kCompressThreads>), gd, bd, 0, st, p); break;
+      case 64: hipLaunchKernelGGL((k_compress<2, kCompressThreads>), gd, bd, 0, st, p); break;
+      case 128: hipLaunchKernelGGL((k_compress<4, kCompressThreads>), gd, bd, 0, st, p); break;
+      case 256: hipLaunchKernelGGL((k_compress<8, kCompressThreads>), gd, bd, 0, st, p); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else {  // a small field: no more small tiles than CUs, each its own workgroup
+    const dim3 gd = dim3(uint32_t(ntiles)), bd = dim3(kSmallTileSegs);
+    switch (g.L) {
+      case 32: hipLaunchKernelGGL((k_compress<1, kSmallTileSegs>), gd, bd, 0, st, p); break;
+      case 64: hipLaunchKernelGGL((k_compress<2, kSmallTileSegs>), gd, bd, 0, st, p); break;
+      case 128: hipLaunchKernelGGL((k_compress<4, kSmallTileSegs>), gd, bd, 0, st, p); break;
+      case 256: hipLaunchKernelGGL((k_compress<8, kSmallTileSegs>), gd, bd, 0, st, p); break;
+      default: return hipErrorInvalidValue;
+    }
   }
   return hipGetLastError();
 }
@@ -2898,6 +2912,7 @@ hipError_t query_grids(Grids& gr, int num_cus) {
   gr.reduce = clampg(r);
   gr.add = clampg(a);
   gr.mul = clampg(m);
+  gr.cus = num_cus;
   gr.negate = num_cus;  // one workgroup per CU: fewer end-of-kernel atomics, measured fastest
   gr.widths = num_cus;
   gr.f32 = num_cus * 4;

@@ -20,8 +20,9 @@
 
 namespace {
 
-// Look-back status words: one per compress tile of kCompressTileSegs
-// segments (32 slots each); n <= 2^28 gives at most 2^23 / kCompressTileSegs
+// Look-back status words: one per compress tile (32 slots per segment, tiles
+// of kCompressTileSegs segments, or kSmallTileSegs for fields of at most one
+// small tile per compute unit); n <= 2^28 gives at most 2^23 / kCompressTileSegs
 // + 1 tiles (a partial last block adds at most 8 segments).
 constexpr uint64_t kLbWords = (uint64_t(1) << 23) / hz::kCompressTileSegs + 8;
 constexpr uint64_t kCtrlWords = 64;  // ctrl (32 x u32) and acc (32 x u64), 256 B each
@@ -103,7 +104,9 @@ extern "C" int hoszp_compress_noalloc(const float* d_x, uint64_t n, double eb, u
   // caller's stream: no memset node, and a captured graph clears them again
   // on every replay, so the look-back never sees a previous call's prefixes
   // (the kernel's generation counter restarts at 1 with them).
-  const uint64_t tiles = (g.nseg + hz::kCompressTileSegs - 1) / hz::kCompressTileSegs;
+  const uint32_t nt = hz::compress_tile_segs(g.nseg, d.grids.cus);
+  const uint64_t tiles = (g.nseg + nt - 1) / nt;
+  if (tiles > kLbWords) return HOSZP_ERR_LIMIT;  // (only on a GPU with over 8000 CUs)
   hipLaunchKernelGGL(k_noalloc_clear, dim3(8), dim3(256), 0, st, d.ptr, kCtrlWords + tiles);
   if (hipGetLastError() != hipSuccess) return HOSZP_ERR_DEVICE;
   const double inv2e = 1.0 / (2.0 * eb);

@@ -19,7 +19,7 @@ import paper_2408_11971_amd as hz  # noqa: E402
 pytestmark = pytest.mark.gpu
 
 N_MULTI = 200_003   # 6251 segments of 32: several 1024-segment encoder tiles
-N_SINGLE = 30_000   # 938 segments: one tile
+N_SINGLE = 8_000    # 250 segments: one tile at every tile size (256, 512, 1024)
 L, EB = 32, 1e-3
 
 
