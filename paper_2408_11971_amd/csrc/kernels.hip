@@ -2078,14 +2078,6 @@ struct MulParams {
   hoszp_result* res;
 };
 
-// One scaled bin (mul_round) with the range check of the output bin.
-__device__ __forceinline__ int32_t scaled_bin(int32_t q, double s, uint32_t& bad) {
-  const double f = mul_round(s, double(q));
-  const bool ok = fabs(f) <= kBinMaxD;
-  bad |= ok ? 0u : uint32_t(ST_RANGE);
-  return ok ? int32_t(f) : 0;
-}
-
 // Scale a segment's bins front to back and turn each at once into its output
 // delta's magnitude and sign, so an input bin dies as its delta is made.
 // The scaled bins z_j = mul_round(s, q_j) are integers, so the delta
