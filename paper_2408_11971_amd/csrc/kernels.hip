@@ -443,10 +443,18 @@ __device__ __forceinline__ uint64_t tile_offset(const TileIndex& ix, uint64_t ti
   // chunk's first word and drop it)
   const uint32_t t = ix.tile_words[chunk * kChunkTiles + (uint32_t(lane) < r ? lane : 0)];
   const uint64_t c = ix.chunk_off[chunk];
-  return c + wave_sum(uint32_t(lane) < r ? uint64_t(t) : 0u);
+  // a wave tile holds at most 64 x 32 words, so 63 of them sum below 2^17
+  return c + wave_sum32(uint32_t(lane) < r ? t : 0u);
 }
 
 // ------------------------------------------------------ segment primitives
+
+// Number of valid slots (0..32) of segment `seg` from nfull = n / 32 and
+// tail = n % 32: segment seg holds the slots 32 seg .. 32 seg + 31 of the
+// field, as every block is a whole number of segments.
+__device__ __forceinline__ uint32_t seg_valid(uint64_t seg, uint64_t nfull, uint32_t tail) {
+  return seg < nfull ? 32u : (seg == nfull ? tail : 0u);
+}
 
 // Number of valid slots (0..32) of segment `sub` of block `blk`.
 __device__ __forceinline__ uint32_t seg_count(const Layout& g, uint64_t blk, uint32_t sub,
@@ -462,6 +470,19 @@ __device__ __forceinline__ uint32_t seg_count(const Layout& g, uint64_t blk, uin
 __device__ __forceinline__ uint32_t window_at(const uint32_t* sp, uint32_t p) {
   const uint32_t i = (p + 31u) >> 5;  // the 32 bits from bit p on (MSB first)
   return __builtin_amdgcn_alignbit(sp[int(i) - 1], sp[i], 0u - p);
+}
+// p + 31 for field j's start bit p = j w (w <= 32, j < 32), as one
+// instruction on the full-rate 24-bit multiplier: left to itself the compiler
+// turns j w with a constant j into quarter-rate 32-bit multiplies.
+__device__ __forceinline__ uint32_t field_q(uint32_t w, uint32_t j) {
+  uint32_t q;
+  asm("v_mad_u32_u24 %0, %1, %2, 31" : "=v"(q) : "v"(w), "s"(j));
+  return q;
+}
+// window_at from q = p + 31 (~q equals -p modulo 32).
+__device__ __forceinline__ uint32_t window_q(const uint32_t* sp, uint32_t q) {
+  const uint32_t i = q >> 5;
+  return __builtin_amdgcn_alignbit(sp[int(i) - 1], sp[i], ~q);
 }
 __device__ __forceinline__ uint32_t field_at(const uint32_t* sp, uint32_t p, uint32_t rshift) {
   return window_at(sp, p) >> rshift;
@@ -541,6 +562,13 @@ __device__ __forceinline__ bool bins_surely_in_range(int64_t outlier, uint64_t b
   const uint64_t a = uint64_t(outlier < 0 ? -outlier : outlier);
   const uint64_t step = (uint64_t(1) << w) - 1;
   return a + (blen - 1) * step <= uint64_t(kBinMax);
+}
+// The same test for any block of at most L slots (w <= 32), on 32-bit
+// operands: one 32 x 32 -> 64-bit multiply-add.
+__device__ __forceinline__ bool bins_in_range_upto(int32_t outlier, uint32_t L, uint32_t w) {
+  const uint32_t a = outlier < 0 ? 0u - uint32_t(outlier) : uint32_t(outlier);
+  const uint32_t step = w ? 0xffffffffu >> (32u - w) : 0u;
+  return uint64_t(L - 1u) * step + a <= uint64_t(kBinMax);
 }
 
 // Stage na words from a, then nb words from b, into LDS as big-endian-decoded
@@ -689,32 +717,39 @@ struct WidthParams {
   Scratch s;
 };
 
-// Payload words of the 16 segments seg0 .. seg0+15 (those below nseg): each
-// segment counts its block's width.  Widths above 32 are flagged (and
-// counted as 0).  seg0 is a multiple of 16, so the width bytes are aligned.
-__device__ __forceinline__ uint32_t widths_of_16(const uint8_t* c, const Layout& g, uint64_t seg0,
-                                                 uint32_t& bad) {
-  if (seg0 >= g.nseg) return 0;
+// Width bytes of the blocks of the 16 segments seg0 .. seg0+15, packed four
+// to a word (zero past the last block).  seg0 is a multiple of 16, so the
+// width bytes are aligned.
+__device__ __forceinline__ uint4 widths_raw16(const uint8_t* c, const Layout& g, uint64_t seg0) {
+  uint4 q = make_uint4(0u, 0u, 0u, 0u);
+  if (seg0 >= g.nseg) return q;
   const uint8_t* W = c + g.off_w;
   const uint64_t b0 = seg0 >> g.spb_log2;               // first block
   const uint64_t nbk = 16u >> g.spb_log2;                // blocks covered when whole
   const uint64_t have = g.nb - b0 < nbk ? g.nb - b0 : nbk;
-  uint32_t q[4] = {0, 0, 0, 0};
   if (have == nbk) {
     if (nbk == 16) {
-      const uint4 v = *reinterpret_cast<const uint4*>(W + b0);
-      q[0] = v.x, q[1] = v.y, q[2] = v.z, q[3] = v.w;
+      q = *reinterpret_cast<const uint4*>(W + b0);
     } else if (nbk == 8) {
       const uint2 v = *reinterpret_cast<const uint2*>(W + b0);
-      q[0] = v.x, q[1] = v.y;
+      q.x = v.x, q.y = v.y;
     } else if (nbk == 4) {
-      q[0] = *reinterpret_cast<const uint32_t*>(W + b0);
+      q.x = *reinterpret_cast<const uint32_t*>(W + b0);
     } else {  // block 256: two blocks, b0 even
-      q[0] = *reinterpret_cast<const uint16_t*>(W + b0);
+      q.x = *reinterpret_cast<const uint16_t*>(W + b0);
     }
   } else {
-    for (uint32_t k = 0; k < uint32_t(have); ++k) q[k >> 2] |= uint32_t(W[b0 + k]) << (8 * (k & 3));
+    uint32_t t[4] = {0, 0, 0, 0};
+    for (uint32_t k = 0; k < uint32_t(have); ++k) t[k >> 2] |= uint32_t(W[b0 + k]) << (8 * (k & 3));
+    q = make_uint4(t[0], t[1], t[2], t[3]);
   }
+  return q;
+}
+
+// Payload words of those segments from their width bytes: each segment
+// counts its block's width (widths above 32 are reported and counted as 0).
+__device__ __forceinline__ uint32_t widths_sum16(uint4 q4, uint32_t spb, uint32_t& bad) {
+  const uint32_t q[4] = {q4.x, q4.y, q4.z, q4.w};
   uint32_t sum = 0;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
@@ -731,15 +766,21 @@ __device__ __forceinline__ uint32_t widths_of_16(const uint8_t* c, const Layout&
     }
     sum = __builtin_amdgcn_sad_u8(packed, 0u, sum);  // adds the 4 bytes
   }
-  return sum * g.spb;
+  return sum * spb;
 }
 
 // Width pre-pass of a stream (reads only its width section): payload words of
 // every wave tile and the exclusive prefix of every chunk of kChunkTiles wave
 // tiles, so decoders locate any tile's payload without a serial scan.  Also
 // checks every width <= 32 and that the widths fill the payload exactly.
+// A workgroup takes kWidthChunks chunks per pass with all their loads in
+// flight at once; the last workgroup to finish turns the chunk counts into
+// offsets, holding up to kOffRegs counts per thread in registers so each is
+// read once.
+constexpr int kWidthChunks = 4;
+constexpr int kOffRegs = 8;
 __global__ void __launch_bounds__(kThreads) k_widths(WidthParams p) {
-  __shared__ uint32_t s_chunk[kThreads / 64];
+  __shared__ uint32_t s_chunk[kWidthChunks][kThreads / 64];
   __shared__ uint64_t s_tmp[kThreads / 64];
   __shared__ uint32_t s_flag;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -752,21 +793,29 @@ __global__ void __launch_bounds__(kThreads) k_widths(WidthParams p) {
   static_assert(kChunkTiles * kWaveSegs == kThreads * 16, "16 segments per thread per chunk");
   const uint64_t nchunks = (g.nwtiles + kChunkTiles - 1) / kChunkTiles;
   uint32_t bad = 0;
-  for (uint64_t chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
-    // thread tid: segments 16 tid .. 16 tid + 15 of the chunk, a quarter of
+  for (uint64_t c0 = uint64_t(blockIdx.x) * kWidthChunks; c0 < nchunks;
+       c0 += uint64_t(gridDim.x) * kWidthChunks) {
+    // thread tid: segments 16 tid .. 16 tid + 15 of each chunk, a quarter of
     // wave tile tid / 4
-    uint32_t v = widths_of_16(p.c, g, chunk * (kChunkTiles * kWaveSegs) + 16 * uint64_t(tid), bad);
-    v += __shfl_xor(v, 1, 64);
-    v += __shfl_xor(v, 2, 64);
-    const uint64_t wt = chunk * kChunkTiles + uint64_t(tid >> 2);
-    if ((tid & 3) == 0 && wt < g.nwtiles) p.ix.tile_words[wt] = v;
-    const uint32_t wsum = wave_sum32((tid & 3) == 0 ? v : 0u);
-    if (lane == 0) s_chunk[wave] = wsum;
+    uint4 q[kWidthChunks];
+#pragma unroll
+    for (int k = 0; k < kWidthChunks; ++k)
+      q[k] = widths_raw16(p.c, g, (c0 + k) * (kChunkTiles * kWaveSegs) + 16 * uint64_t(tid));
+#pragma unroll
+    for (int k = 0; k < kWidthChunks; ++k) {
+      uint32_t v = widths_sum16(q[k], g.spb, bad);
+      v += __shfl_xor(v, 1, 64);
+      v += __shfl_xor(v, 2, 64);
+      const uint64_t wt = (c0 + k) * kChunkTiles + uint64_t(tid >> 2);
+      if ((tid & 3) == 0 && wt < g.nwtiles) p.ix.tile_words[wt] = v;
+      const uint32_t wsum = wave_sum32((tid & 3) == 0 ? v : 0u);
+      if (lane == 0) s_chunk[k][wave] = wsum;
+    }
     __syncthreads();
-    if (tid == 0) {
+    if (tid < kWidthChunks && c0 + tid < nchunks) {
       uint32_t t = 0;
-      for (int k = 0; k < kThreads / 64; ++k) t += s_chunk[k];
-      st_dev32(&p.ix.chunk_words[chunk], t);
+      for (int k = 0; k < kThreads / 64; ++k) t += s_chunk[tid][k];
+      st_dev32(&p.ix.chunk_words[c0 + tid], t);
     }
     __syncthreads();
   }
@@ -775,13 +824,28 @@ __global__ void __launch_bounds__(kThreads) k_widths(WidthParams p) {
   // last workgroup: chunk counts -> chunk offsets, and the total check
   const uint64_t per = (nchunks + kThreads - 1) / kThreads;
   const uint64_t lo = per * tid, hi = lo + per < nchunks ? lo + per : nchunks;
-  uint64_t local = 0;
-  for (uint64_t c = lo; c < hi; ++c) local += ld_dev32(&p.ix.chunk_words[c]);
   uint64_t total;
-  uint64_t run = wg_scan64(local, total, s_tmp);
-  for (uint64_t c = lo; c < hi; ++c) {
-    p.ix.chunk_off[c] = run;
-    run += ld_dev32(&p.ix.chunk_words[c]);
+  if (per <= uint64_t(kOffRegs)) {
+    uint32_t cw[kOffRegs];
+#pragma unroll
+    for (int k = 0; k < kOffRegs; ++k) cw[k] = lo + k < hi ? ld_dev32(&p.ix.chunk_words[lo + k]) : 0u;
+    uint64_t local = 0;
+#pragma unroll
+    for (int k = 0; k < kOffRegs; ++k) local += cw[k];
+    uint64_t run = wg_scan64(local, total, s_tmp);
+#pragma unroll
+    for (int k = 0; k < kOffRegs; ++k) {
+      if (lo + k < hi) p.ix.chunk_off[lo + k] = run;
+      run += cw[k];
+    }
+  } else {
+    uint64_t local = 0;
+    for (uint64_t c = lo; c < hi; ++c) local += ld_dev32(&p.ix.chunk_words[c]);
+    uint64_t run = wg_scan64(local, total, s_tmp);
+    for (uint64_t c = lo; c < hi; ++c) {
+      p.ix.chunk_off[c] = run;
+      run += ld_dev32(&p.ix.chunk_words[c]);
+    }
   }
   if (tid == 0) {
     if (total != g.payload_bytes / 4) latch(p.s, ST_FORMAT);
@@ -1238,7 +1302,6 @@ __device__ __forceinline__ int32_t mean_fast(const uint32_t* sp, uint32_t w, uin
                                              bool first_seg, int32_t& D) {
   const uint32_t rs = 32u - w;
   int32_t run = 0, acc = 0;
-  uint32_t pbit = 0;
   auto step = [&](int32_t m, int j) {
     int32_t x = m ^ (int32_t(signs << j) >> 31);
     if (j == 0 && first_seg) x = 0;
@@ -1247,10 +1310,9 @@ __device__ __forceinline__ int32_t mean_fast(const uint32_t* sp, uint32_t w, uin
   };
 #pragma unroll
   for (int j = 0; j < 32; j += PAIR ? 2 : 1) {
-    const uint32_t win = window_at(sp, pbit);
-    pbit += PAIR ? 2 * w : w;
+    const uint32_t win = window_q(sp, field_q(w, uint32_t(j)));  // field j starts at bit j w
     step(int32_t(win >> rs), j);
-    if (PAIR) step(int32_t((win << w) >> rs), j + 1);
+    if (PAIR) step(int32_t(__builtin_amdgcn_ubfe(win, rs - w, w)), j + 1);  // bits 32-2w .. 31-w
   }
   D = run + int32_t(__popc(signs));
   return acc + int32_t(weighted_popcount(signs));
@@ -1264,7 +1326,6 @@ __device__ __forceinline__ void var_fast(const uint32_t* sp, uint32_t w, uint32_
   const uint32_t rs = 32u - w;
   int32_t e = 0, s1 = 0;
   int64_t s2 = 0;
-  uint32_t pbit = 0;
   auto step = [&](int32_t m, int j) {
     const int32_t neg = int32_t(sw << j) >> 31;
     int32_t d = (m ^ neg) - neg;
@@ -1275,10 +1336,9 @@ __device__ __forceinline__ void var_fast(const uint32_t* sp, uint32_t w, uint32_
   };
 #pragma unroll
   for (int j = 0; j < 32; j += PAIR ? 2 : 1) {
-    const uint32_t win = window_at(sp, pbit);
-    pbit += PAIR ? 2 * w : w;
+    const uint32_t win = window_q(sp, field_q(w, uint32_t(j)));  // field j starts at bit j w
     step(int32_t(win >> rs), j);
-    if (PAIR) step(int32_t((win << w) >> rs), j + 1);
+    if (PAIR) step(int32_t(__builtin_amdgcn_ubfe(win, rs - w, w)), j + 1);  // bits 32-2w .. 31-w
   }
   E = s1;
   E2 = s2;
@@ -1287,12 +1347,11 @@ __device__ __forceinline__ void var_fast(const uint32_t* sp, uint32_t w, uint32_
 
 // Fast path of a full segment (width 1..20) for decompression: the in-segment
 // prefixes (modulo 2^32; the bins they lead to are int32).
-template <bool PAIR>
+template <bool PAIR, bool MAD = false>
 __device__ __forceinline__ int32_t prefix_fast(const uint32_t* sp, uint32_t w, uint32_t sw,
                                                bool first_seg, int32_t* e_out) {
   const uint32_t rs = 32u - w;
   int32_t e = 0;
-  uint32_t pbit = 0;
   auto step = [&](int32_t m, int j) {
     const int32_t neg = int32_t(sw << j) >> 31;
     int32_t d = (m ^ neg) - neg;
@@ -1302,10 +1361,11 @@ __device__ __forceinline__ int32_t prefix_fast(const uint32_t* sp, uint32_t w, u
   };
 #pragma unroll
   for (int j = 0; j < 32; j += PAIR ? 2 : 1) {
-    const uint32_t win = window_at(sp, pbit);
-    pbit += PAIR ? 2 * w : w;
+    // field j starts at bit j w (MAD: on the 24-bit multiplier; the kernels
+    // with the most registers in use keep the compiler's own form)
+    const uint32_t win = MAD ? window_q(sp, field_q(w, uint32_t(j))) : window_at(sp, __umul24(w, uint32_t(j)));
     step(int32_t(win >> rs), j);
-    if (PAIR) step(int32_t((win << w) >> rs), j + 1);
+    if (PAIR) step(int32_t(__builtin_amdgcn_ubfe(win, rs - w, w)), j + 1);  // bits 32-2w .. 31-w
   }
   return e;
 }
@@ -1392,16 +1452,14 @@ __device__ __forceinline__ void meta_b(const Layout& g, const uint32_t* S, const
     w = 0;
   }
   const uint64_t seg = wt * kWaveSegs + lane;
-  const uint64_t blk = (seg >> g.spb_log2);
-  const uint32_t sub = uint32_t(seg & (g.spb - 1));
-  uint64_t blen = 0;
-  const uint32_t cnt = (wt < nwt && seg < g.nseg) ? seg_count(g, blk, sub, blen) : 0u;
+  const uint32_t cnt = wt < nwt ? seg_valid(seg, g.n >> 5, uint32_t(g.n & 31u)) : 0u;
   const uint32_t x = wave_incl_scan(w);  // inclusive scan of the widths over the wave
   m.w = w;
   m.off = x - w;
   m.words = lane_of(x, 63);
   m.outlier = a.outlier;
-  m.base = a.chunk_off + wave_sum(uint64_t(a.tw));
+  // a wave tile holds at most 64 x 32 words, so 63 of them sum below 2^17
+  m.base = a.chunk_off + wave_sum32(a.tw);
   m.sw = (cnt > 0 && w > 0) ? S[seg] : 0u;
   if (m.base + m.words > payload_words) {
     bad |= ST_FORMAT;
@@ -1457,6 +1515,8 @@ __global__ void __launch_bounds__(decode_threads(MODE))
   uint32_t bad = 0, nconst = 0;
   const uint64_t stride = uint64_t(gridDim.x) * (NT / 64);
   const uint64_t wt0 = uint64_t(blockIdx.x) * (NT / 64) + wave;
+  const uint64_t nfull = g.n >> 5;  // full segments; the next holds tail slots
+  const uint32_t tail = uint32_t(g.n & 31u);
   MetaA a1, a2;
   MetaB b0;
   if (wt0 < nwt) {
@@ -1488,11 +1548,9 @@ __global__ void __launch_bounds__(decode_threads(MODE))
     a1 = a2;
 
     const uint64_t seg = wt * kWaveSegs + lane;
-    const bool active = seg < g.nseg;
     const uint64_t blk = (seg >> g.spb_log2);
     const uint32_t sub = uint32_t(seg & (g.spb - 1));
-    uint64_t blen = 0;
-    const uint32_t cnt = active ? seg_count(g, blk, sub, blen) : 0u;
+    const uint32_t cnt = seg_valid(seg, nfull, tail);
 
     const uint32_t* sp = &wp[1 + off];
     const bool fast = cnt == 32 && w <= 20;
@@ -1528,14 +1586,14 @@ __global__ void __launch_bounds__(decode_threads(MODE))
       } else {
         // one field per window here: the paired read costs the registers
         // that keep decompression at 3 waves per SIMD
-        D = prefix_fast<false>(sp, w, sw, sub == 0, keep32);
+        D = prefix_fast<false, true>(sp, w, sw, sub == 0, keep32);
       }
     } else if (cnt > 0) {
       D = decode_generic<MODE == kDecompress, int32_t>(sp, sw, w, sub, cnt, E, E2w, keep32);
     }
     const int64_t carry = int64_t(outlier) + block_excl(D, g.spb);
     // every bin must be a valid int32 bin (slot 0 is the outlier itself)
-    if (cnt > 0 && !bins_surely_in_range(outlier, blen, w)) {
+    if (cnt > 0 && !bins_in_range_upto(outlier, g.L, w)) {
       int64_t e = 0;
       for (int j = 0; j < int(cnt); ++j) {
         if (w && !(j == 0 && sub == 0)) e += seg_delta(sp, sw, w, j);
@@ -1588,6 +1646,8 @@ __global__ void __launch_bounds__(decode_threads(MODE))
       acc_s += bs;
       for (uint32_t m = 1; m < g.spb; m <<= 1) bs += __shfl_xor(bs, int(m), 64);
       if (cnt > 0 && sub == 0) {
+        const uint64_t left = g.n - blk * g.L;
+        const uint64_t blen = left < g.L ? left : g.L;
         p.means[blk] = (double(bs) / double(blen)) * two_eb;
         nconst += w == 0 ? 1u : 0u;
       }
