@@ -93,6 +93,14 @@ __device__ __forceinline__ uint32_t wave_min(uint32_t v) {
   v = min(v, swz_xor<16>(v));
   return min(lane_of(v, 0), lane_of(v, 32));
 }
+__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
+  v = max(v, swz_xor<1>(v));
+  v = max(v, swz_xor<2>(v));
+  v = max(v, swz_xor<4>(v));
+  v = max(v, swz_xor<8>(v));
+  v = max(v, swz_xor<16>(v));
+  return max(lane_of(v, 0), lane_of(v, 32));
+}
 __device__ __forceinline__ uint32_t wave_sum32(uint32_t v) {
   v += swz_xor<1>(v);
   v += swz_xor<2>(v);
@@ -1295,9 +1303,10 @@ __device__ __forceinline__ uint32_t weighted_popcount(uint32_t v) {
 // The same pass also yields D = the delta total (sum_i x_i + popcount(signs),
 // slot 0 of a block excluded).  sum_i (32 - i) x_i is accumulated as the sum
 // of the running prefixes of x, one dependent add each, so no field value
-// outlives its own step.  PAIR (width <= 16): one 32-bit window holds two
-// whole fields, so one LDS read and funnel shift serve both.
-template <bool PAIR>
+// outlives its own step.  G fields per 32-bit window (G w <= 32): one LDS
+// read and funnel shift serve G fields, each then one shift or bit-field
+// extract.
+template <int G>
 __device__ __forceinline__ int32_t mean_fast(const uint32_t* sp, uint32_t w, uint32_t signs,
                                              bool first_seg, int32_t& D) {
   const uint32_t rs = 32u - w;
@@ -1309,22 +1318,26 @@ __device__ __forceinline__ int32_t mean_fast(const uint32_t* sp, uint32_t w, uin
     acc += run;
   };
 #pragma unroll
-  for (int j = 0; j < 32; j += PAIR ? 2 : 1) {
+  for (int j = 0; j < 32; j += G) {
     const uint32_t win = window_q(sp, field_q(w, uint32_t(j)));  // field j starts at bit j w
     step(int32_t(win >> rs), j);
-    if (PAIR) step(int32_t(__builtin_amdgcn_ubfe(win, rs - w, w)), j + 1);  // bits 32-2w .. 31-w
+#pragma unroll
+    for (int k = 1; k < G; ++k)  // field j + k: bits 32 - (k+1) w .. 31 - k w of the window
+      if (j + k < 32) step(int32_t(__builtin_amdgcn_ubfe(win, rs - uint32_t(k) * w, w)), j + k);
   }
   D = run + int32_t(__popc(signs));
   return acc + int32_t(weighted_popcount(signs));
 }
 
 // Fast path of a full segment (width 1..20) for the variance: E = sum e_j
-// (int32), E2 = sum e_j^2 (int64), D = delta total.
-template <bool PAIR>
+// (int32), E2 = sum e_j^2 (int64), D = delta total; G as for the mean.  With
+// G = 4 (w <= 8) every |e_j| <= 31 * 255, so the squares and their sum stay
+// below 2^31 and are formed on the 24-bit multiplier in 32 bits.
+template <int G>
 __device__ __forceinline__ void var_fast(const uint32_t* sp, uint32_t w, uint32_t sw,
                                          bool first_seg, int32_t& E, int64_t& E2, int32_t& D) {
   const uint32_t rs = 32u - w;
-  int32_t e = 0, s1 = 0;
+  int32_t e = 0, s1 = 0, s2n = 0;
   int64_t s2 = 0;
   auto step = [&](int32_t m, int j) {
     const int32_t neg = int32_t(sw << j) >> 31;
@@ -1332,16 +1345,21 @@ __device__ __forceinline__ void var_fast(const uint32_t* sp, uint32_t w, uint32_
     if (j == 0 && first_seg) d = 0;
     e += d;
     s1 += e;
-    s2 += int64_t(e) * e;
+    if (G == 4)
+      s2n += __mul24(e, e);
+    else
+      s2 += int64_t(e) * e;
   };
 #pragma unroll
-  for (int j = 0; j < 32; j += PAIR ? 2 : 1) {
+  for (int j = 0; j < 32; j += G) {
     const uint32_t win = window_q(sp, field_q(w, uint32_t(j)));  // field j starts at bit j w
     step(int32_t(win >> rs), j);
-    if (PAIR) step(int32_t(__builtin_amdgcn_ubfe(win, rs - w, w)), j + 1);  // bits 32-2w .. 31-w
+#pragma unroll
+    for (int k = 1; k < G; ++k)
+      if (j + k < 32) step(int32_t(__builtin_amdgcn_ubfe(win, rs - uint32_t(k) * w, w)), j + k);
   }
   E = s1;
-  E2 = s2;
+  E2 = G == 4 ? int64_t(s2n) : s2;
   D = e;
 }
 
@@ -1419,12 +1437,17 @@ struct MetaA {
 
 // The same tile one step later: scanned widths, sign word and the first
 // payload words, issued one tile ahead of use.
-constexpr int kPrefetchWords = 8;  // payload words per lane held in registers
+// PF payload words per lane are held in registers (measured: 12 for
+// decompression, whose tiles then rarely need a second round trip; 8 for the
+// reductions, which run at the 128-VGPR cap and lose more to the extra
+// registers than they gain).
+template <int PF>
 struct MetaB {
   uint32_t w, off, words, sw;
+  uint32_t wmax;  // largest width of the tile (wave-uniform)
   int32_t outlier;
   uint64_t base;
-  uint32_t pf[kPrefetchWords];
+  uint32_t pf[PF];
 };
 
 __device__ __forceinline__ void meta_a(const Layout& g, const uint8_t* W, const int32_t* O,
@@ -1442,9 +1465,10 @@ __device__ __forceinline__ void meta_a(const Layout& g, const uint8_t* W, const 
   m.chunk_off = wt < nwt ? ix.chunk_off[chunk] : 0u;
 }
 
+template <int PF>
 __device__ __forceinline__ void meta_b(const Layout& g, const uint32_t* S, const uint32_t* P,
                                        uint64_t payload_words, uint64_t wt, uint64_t nwt,
-                                       const MetaA& a, MetaB& m, uint32_t& bad) {
+                                       const MetaA& a, MetaB<PF>& m, uint32_t& bad) {
   const int lane = threadIdx.x & 63;
   uint32_t w = a.w;
   if (w > 32) {
@@ -1457,6 +1481,7 @@ __device__ __forceinline__ void meta_b(const Layout& g, const uint32_t* S, const
   m.w = w;
   m.off = x - w;
   m.words = lane_of(x, 63);
+  m.wmax = wave_max(w);
   m.outlier = a.outlier;
   // a wave tile holds at most 64 x 32 words, so 63 of them sum below 2^17
   m.base = a.chunk_off + wave_sum32(a.tw);
@@ -1466,7 +1491,7 @@ __device__ __forceinline__ void meta_b(const Layout& g, const uint32_t* S, const
     m.words = 0;
   }
 #pragma unroll
-  for (int k = 0; k < kPrefetchWords; ++k) {
+  for (int k = 0; k < PF; ++k) {
     const uint32_t i = uint32_t(lane) + 64u * k;
     m.pf[k] = i < m.words ? P[m.base + i] : 0u;
   }
@@ -1518,7 +1543,8 @@ __global__ void __launch_bounds__(decode_threads(MODE))
   const uint64_t nfull = g.n >> 5;  // full segments; the next holds tail slots
   const uint32_t tail = uint32_t(g.n & 31u);
   MetaA a1, a2;
-  MetaB b0;
+  constexpr int PF = MODE == kDecompress ? 12 : 8;
+  MetaB<PF> b0;
   if (wt0 < nwt) {
     MetaA a0;
     meta_a(g, W, O, p.s.idx[0], wt0, nwt, a0);
@@ -1530,18 +1556,18 @@ __global__ void __launch_bounds__(decode_threads(MODE))
     // stage this tile's payload (prefetched words first)
     const uint32_t words = b0.words;
 #pragma unroll
-    for (int k = 0; k < kPrefetchWords; ++k) {
+    for (int k = 0; k < PF; ++k) {
       const uint32_t i = uint32_t(lane) + 64u * k;
       if (i < words) wp[1 + i] = bswap32(b0.pf[k]);
     }
-    for (uint32_t i = lane + 64u * kPrefetchWords; i < words; i += 64)
+    for (uint32_t i = lane + 64u * PF; i < words; i += 64)
       wp[1 + i] = bswap32(P[b0.base + i]);
     if (lane == 0) {
       wp[0] = 0;
       wp[1 + words] = 0;
     }
     __builtin_amdgcn_wave_barrier();  // LDS operations of one wave complete in order
-    const uint32_t w = b0.w, off = b0.off, sw = bswap32(b0.sw);
+    const uint32_t w = b0.w, off = b0.off, sw = bswap32(b0.sw), wmax = b0.wmax;
     const int32_t outlier = b0.outlier;
     // the next tile's sign words and payload are in flight during this tile
     meta_b(g, S, P, payload_words, wt + stride, nwt, a1, b0, bad);
@@ -1570,16 +1596,26 @@ __global__ void __launch_bounds__(decode_threads(MODE))
       } else if (MODE == kMean || MODE == kBlockMean) {
         const uint32_t signs = sub == 0 ? (sw & 0x7fffffffu) : sw;  // slot 0: the outlier
         int32_t d1;
-        E = w <= 16 ? mean_fast<true>(sp, w, signs, sub == 0, d1)
-                    : mean_fast<false>(sp, w, signs, sub == 0, d1);
+        if (wmax <= 8)
+          E = mean_fast<4>(sp, w, signs, sub == 0, d1);
+        else if (wmax <= 10)
+          E = mean_fast<3>(sp, w, signs, sub == 0, d1);
+        else if (wmax <= 16)
+          E = mean_fast<2>(sp, w, signs, sub == 0, d1);
+        else
+          E = mean_fast<1>(sp, w, signs, sub == 0, d1);
         D = d1;
       } else if (MODE == kVariance) {
         int32_t e1, d1;
         int64_t e2;
-        if (w <= 16)
-          var_fast<true>(sp, w, sw, sub == 0, e1, e2, d1);
+        if (wmax <= 8)
+          var_fast<4>(sp, w, sw, sub == 0, e1, e2, d1);
+        else if (wmax <= 10)
+          var_fast<3>(sp, w, sw, sub == 0, e1, e2, d1);
+        else if (wmax <= 16)
+          var_fast<2>(sp, w, sw, sub == 0, e1, e2, d1);
         else
-          var_fast<false>(sp, w, sw, sub == 0, e1, e2, d1);
+          var_fast<1>(sp, w, sw, sub == 0, e1, e2, d1);
         E = e1;
         E2 = uint64_t(e2);
         D = d1;
