@@ -93,14 +93,6 @@ __device__ __forceinline__ uint32_t wave_min(uint32_t v) {
   v = min(v, swz_xor<16>(v));
   return min(lane_of(v, 0), lane_of(v, 32));
 }
-__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
-  v = max(v, swz_xor<1>(v));
-  v = max(v, swz_xor<2>(v));
-  v = max(v, swz_xor<4>(v));
-  v = max(v, swz_xor<8>(v));
-  v = max(v, swz_xor<16>(v));
-  return max(lane_of(v, 0), lane_of(v, 32));
-}
 __device__ __forceinline__ uint32_t wave_sum32(uint32_t v) {
   v += swz_xor<1>(v);
   v += swz_xor<2>(v);
@@ -148,6 +140,23 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
   t = dpp_mov<0x143>(x);  // row_bcast:31
   x += lane >= 32 ? t : 0u;
   return x;
+}
+
+// Largest value over the wave (every lane active) by the same DPP pattern as
+// the scan, all in VALU (no LDS round trips): lanes without a source lane
+// read 0, which is no larger than any value here.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_or0(uint32_t v) {
+  return uint32_t(__builtin_amdgcn_update_dpp(0, int(v), CTRL, 0xf, 0xf, true));
+}
+__device__ __forceinline__ uint32_t wave_max(uint32_t x) {
+  x = max(x, dpp_or0<0x111>(x));  // row_shr:1
+  x = max(x, dpp_or0<0x112>(x));  // row_shr:2
+  x = max(x, dpp_or0<0x114>(x));  // row_shr:4
+  x = max(x, dpp_or0<0x118>(x));  // row_shr:8
+  x = max(x, dpp_or0<0x142>(x));  // row_bcast:15
+  x = max(x, dpp_or0<0x143>(x));  // row_bcast:31
+  return lane_of(x, 63);
 }
 
 // Count this workgroup as finished on `counter`.  True (uniform) in the last
@@ -781,10 +790,10 @@ __device__ __forceinline__ uint32_t widths_sum16(uint4 q4, uint32_t spb, uint32_
 // every wave tile and the exclusive prefix of every chunk of kChunkTiles wave
 // tiles, so decoders locate any tile's payload without a serial scan.  Also
 // checks every width <= 32 and that the widths fill the payload exactly.
-// A workgroup takes kWidthChunks chunks per pass with all their loads in
-// flight at once; the last workgroup to finish turns the chunk counts into
-// offsets, holding up to kOffRegs counts per thread in registers so each is
-// read once.
+// A workgroup takes up to kWidthChunks chunks per pass, gridDim.x apart (so
+// every workgroup has one before any has two), with all their loads in flight
+// at once; the last workgroup to finish turns the chunk counts into offsets,
+// holding up to kOffRegs counts per thread in registers so each is read once.
 constexpr int kWidthChunks = 4;
 constexpr int kOffRegs = 8;
 __global__ void __launch_bounds__(kThreads) k_widths(WidthParams p) {
@@ -801,29 +810,30 @@ __global__ void __launch_bounds__(kThreads) k_widths(WidthParams p) {
   static_assert(kChunkTiles * kWaveSegs == kThreads * 16, "16 segments per thread per chunk");
   const uint64_t nchunks = (g.nwtiles + kChunkTiles - 1) / kChunkTiles;
   uint32_t bad = 0;
-  for (uint64_t c0 = uint64_t(blockIdx.x) * kWidthChunks; c0 < nchunks;
-       c0 += uint64_t(gridDim.x) * kWidthChunks) {
+  const uint64_t gs = gridDim.x;
+  for (uint64_t c0 = blockIdx.x; c0 < nchunks; c0 += gs * kWidthChunks) {
     // thread tid: segments 16 tid .. 16 tid + 15 of each chunk, a quarter of
-    // wave tile tid / 4
+    // wave tile tid / 4 (chunks past the last read nothing and count 0)
     uint4 q[kWidthChunks];
 #pragma unroll
     for (int k = 0; k < kWidthChunks; ++k)
-      q[k] = widths_raw16(p.c, g, (c0 + k) * (kChunkTiles * kWaveSegs) + 16 * uint64_t(tid));
+      q[k] = widths_raw16(p.c, g, (c0 + k * gs) * (kChunkTiles * kWaveSegs) + 16 * uint64_t(tid));
 #pragma unroll
     for (int k = 0; k < kWidthChunks; ++k) {
+      if (c0 + k * gs >= nchunks) break;  // (uniform) no dependent shuffles for absent chunks
       uint32_t v = widths_sum16(q[k], g.spb, bad);
       v += __shfl_xor(v, 1, 64);
       v += __shfl_xor(v, 2, 64);
-      const uint64_t wt = (c0 + k) * kChunkTiles + uint64_t(tid >> 2);
+      const uint64_t wt = (c0 + k * gs) * kChunkTiles + uint64_t(tid >> 2);
       if ((tid & 3) == 0 && wt < g.nwtiles) p.ix.tile_words[wt] = v;
       const uint32_t wsum = wave_sum32((tid & 3) == 0 ? v : 0u);
       if (lane == 0) s_chunk[k][wave] = wsum;
     }
     __syncthreads();
-    if (tid < kWidthChunks && c0 + tid < nchunks) {
+    if (tid < kWidthChunks && c0 + tid * gs < nchunks) {
       uint32_t t = 0;
       for (int k = 0; k < kThreads / 64; ++k) t += s_chunk[tid][k];
-      st_dev32(&p.ix.chunk_words[c0 + tid], t);
+      st_dev32(&p.ix.chunk_words[c0 + tid * gs], t);
     }
     __syncthreads();
   }
