@@ -2047,7 +2047,7 @@ __global__ void __launch_bounds__(NT) k_add(AddParams p) {
           const uint32_t win = window_at(sp, pa);
           pa += 2 * wa;
           ma[j] = win >> rs;
-          ma[j + 1] = (win << wa) >> rs;
+          ma[j + 1] = __builtin_amdgcn_ubfe(win, rs - wa, wa);
         }
       } else {
 #pragma unroll
@@ -2076,13 +2076,13 @@ __global__ void __launch_bounds__(NT) k_add(AddParams p) {
       uint32_t pb = 0;
       int32_t dsum = 0;
       auto step = [&](int j, int32_t fb) {  // fb: B's magnitude of slot j
+        // sign masks (0 or -1): d = (m_A ^ s_A) - s_A + (m_B ^ s_B) - s_B
         const int32_t sa = int32_t(swa << j) >> 31, sb = int32_t(swb << j) >> 31;
-        int32_t d = ((int32_t(ma[j]) ^ sa) - sa) + ((fb ^ sb) - sb);
+        int32_t d = ((int32_t(ma[j]) ^ sa) + (fb ^ sb)) - (sa + sb);
         if (j == 0 && sub == 0) d = 0;
-        const uint32_t neg = uint32_t(d) >> 31;
-        const uint32_t m = neg ? 0u - uint32_t(d) : uint32_t(d);
+        const uint32_t m = uint32_t(d < 0 ? -d : d);
         mag[j] = m;
-        sgn |= neg << (31 - j);
+        sgn = __builtin_amdgcn_alignbit(sgn, uint32_t(d), 31);  // shift in d's sign: slot j ends at bit 31 - j
         mx = max(mx, m);
         dsum += d;
       };
@@ -2092,7 +2092,7 @@ __global__ void __launch_bounds__(NT) k_add(AddParams p) {
           const uint32_t win = window_at(spb, pb);
           pb += 2 * wb;
           step(j, int32_t(win >> rb));
-          step(j + 1, int32_t((win << wb) >> rb));
+          step(j + 1, int32_t(__builtin_amdgcn_ubfe(win, rb - wb, wb)));
         }
       } else {
 #pragma unroll
