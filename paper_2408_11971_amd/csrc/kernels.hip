@@ -726,12 +726,15 @@ __global__ void k_zero64(uint64_t* p, uint64_t n) {
     p[i] = 0;
 }
 
+// One or two streams (the operands of a two-stream operation are indexed by
+// one launch: the grid's first half takes stream 0, the second stream 1).
 struct WidthParams {
-  const uint8_t* c;
-  uint64_t c_bytes;
-  TileIndex ix;
-  uint32_t* done;  // finished-workgroup counter of this pre-pass
+  const uint8_t* c[2];
+  uint64_t c_bytes[2];
+  TileIndex ix[2];
+  uint32_t* done[2];  // finished-workgroup counter of each stream's pre-pass
   Scratch s;
+  uint32_t nstreams;
 };
 
 // Width bytes of the blocks of the 16 segments seg0 .. seg0+15, packed four
@@ -801,23 +804,27 @@ __global__ void __launch_bounds__(kThreads) k_widths(WidthParams p) {
   __shared__ uint64_t s_tmp[kThreads / 64];
   __shared__ uint32_t s_flag;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint32_t gsz = gridDim.x / p.nstreams;  // workgroups per stream
+  const uint32_t which = blockIdx.x / gsz, bid = blockIdx.x - which * gsz;
+  const uint8_t* c = p.c[which];
+  const TileIndex ix = p.ix[which];
   Layout g;
-  const uint32_t err = read_header(p.c, p.c_bytes, g);
+  const uint32_t err = read_header(c, p.c_bytes[which], g);
   if (err) {  // decoders see the same header and stop; nothing to index
-    if (tid == 0 && blockIdx.x == 0) latch(p.s, err);
+    if (tid == 0 && bid == 0) latch(p.s, err);
     return;
   }
   static_assert(kChunkTiles * kWaveSegs == kThreads * 16, "16 segments per thread per chunk");
   const uint64_t nchunks = (g.nwtiles + kChunkTiles - 1) / kChunkTiles;
   uint32_t bad = 0;
-  const uint64_t gs = gridDim.x;
-  for (uint64_t c0 = blockIdx.x; c0 < nchunks; c0 += gs * kWidthChunks) {
+  const uint64_t gs = gsz;
+  for (uint64_t c0 = bid; c0 < nchunks; c0 += gs * kWidthChunks) {
     // thread tid: segments 16 tid .. 16 tid + 15 of each chunk, a quarter of
     // wave tile tid / 4 (chunks past the last read nothing and count 0)
     uint4 q[kWidthChunks];
 #pragma unroll
     for (int k = 0; k < kWidthChunks; ++k)
-      q[k] = widths_raw16(p.c, g, (c0 + k * gs) * (kChunkTiles * kWaveSegs) + 16 * uint64_t(tid));
+      q[k] = widths_raw16(c, g, (c0 + k * gs) * (kChunkTiles * kWaveSegs) + 16 * uint64_t(tid));
 #pragma unroll
     for (int k = 0; k < kWidthChunks; ++k) {
       if (c0 + k * gs >= nchunks) break;  // (uniform) no dependent shuffles for absent chunks
@@ -825,7 +832,7 @@ __global__ void __launch_bounds__(kThreads) k_widths(WidthParams p) {
       v += __shfl_xor(v, 1, 64);
       v += __shfl_xor(v, 2, 64);
       const uint64_t wt = (c0 + k * gs) * kChunkTiles + uint64_t(tid >> 2);
-      if ((tid & 3) == 0 && wt < g.nwtiles) p.ix.tile_words[wt] = v;
+      if ((tid & 3) == 0 && wt < g.nwtiles) ix.tile_words[wt] = v;
       const uint32_t wsum = wave_sum32((tid & 3) == 0 ? v : 0u);
       if (lane == 0) s_chunk[k][wave] = wsum;
     }
@@ -833,12 +840,12 @@ __global__ void __launch_bounds__(kThreads) k_widths(WidthParams p) {
     if (tid < kWidthChunks && c0 + tid * gs < nchunks) {
       uint32_t t = 0;
       for (int k = 0; k < kThreads / 64; ++k) t += s_chunk[tid][k];
-      st_dev32(&p.ix.chunk_words[c0 + tid * gs], t);
+      st_dev32(&ix.chunk_words[c0 + tid * gs], t);
     }
     __syncthreads();
   }
   latch(p.s, bad);
-  if (!finish_arrive(p.done, &s_flag)) return;
+  if (!finish_arrive_n(p.done[which], 1u, gsz, &s_flag)) return;
   // last workgroup: chunk counts -> chunk offsets, and the total check
   const uint64_t per = (nchunks + kThreads - 1) / kThreads;
   const uint64_t lo = per * tid, hi = lo + per < nchunks ? lo + per : nchunks;
@@ -846,28 +853,28 @@ __global__ void __launch_bounds__(kThreads) k_widths(WidthParams p) {
   if (per <= uint64_t(kOffRegs)) {
     uint32_t cw[kOffRegs];
 #pragma unroll
-    for (int k = 0; k < kOffRegs; ++k) cw[k] = lo + k < hi ? ld_dev32(&p.ix.chunk_words[lo + k]) : 0u;
+    for (int k = 0; k < kOffRegs; ++k) cw[k] = lo + k < hi ? ld_dev32(&ix.chunk_words[lo + k]) : 0u;
     uint64_t local = 0;
 #pragma unroll
     for (int k = 0; k < kOffRegs; ++k) local += cw[k];
     uint64_t run = wg_scan64(local, total, s_tmp);
 #pragma unroll
     for (int k = 0; k < kOffRegs; ++k) {
-      if (lo + k < hi) p.ix.chunk_off[lo + k] = run;
+      if (lo + k < hi) ix.chunk_off[lo + k] = run;
       run += cw[k];
     }
   } else {
     uint64_t local = 0;
-    for (uint64_t c = lo; c < hi; ++c) local += ld_dev32(&p.ix.chunk_words[c]);
+    for (uint64_t c = lo; c < hi; ++c) local += ld_dev32(&ix.chunk_words[c]);
     uint64_t run = wg_scan64(local, total, s_tmp);
     for (uint64_t c = lo; c < hi; ++c) {
-      p.ix.chunk_off[c] = run;
-      run += ld_dev32(&p.ix.chunk_words[c]);
+      ix.chunk_off[c] = run;
+      run += ld_dev32(&ix.chunk_words[c]);
     }
   }
   if (tid == 0) {
     if (total != g.payload_bytes / 4) latch(p.s, ST_FORMAT);
-    *p.done = 0;
+    *p.done[which] = 0;
   }
 }
 
@@ -2824,10 +2831,20 @@ hipError_t launch_reset(const Scratch& s, hoszp_result* res, hipStream_t st) {
   return hipGetLastError();
 }
 
-static hipError_t launch_widths(const Scratch& s, const Grids& gr, int which, const uint8_t* c,
+static hipError_t launch_widths(const Scratch& s, const Grids& gr, const uint8_t* c,
                                 uint64_t c_bytes, hipStream_t st) {
-  WidthParams p{c, c_bytes, s.idx[which], s.ctrl + C_WIDTHS + which, s};
+  WidthParams p{{c, c}, {c_bytes, c_bytes}, {s.idx[0], s.idx[0]},
+                {s.ctrl + C_WIDTHS, s.ctrl + C_WIDTHS}, s, 1u};
   hipLaunchKernelGGL(k_widths, dim3(gr.widths), dim3(kThreads), 0, st, p);
+  return hipGetLastError();
+}
+// Both operands of a two-stream operation in one launch (index 0 and 1).
+static hipError_t launch_widths2(const Scratch& s, const Grids& gr, const uint8_t* a,
+                                 uint64_t a_bytes, const uint8_t* b, uint64_t b_bytes,
+                                 hipStream_t st) {
+  WidthParams p{{a, b}, {a_bytes, b_bytes}, {s.idx[0], s.idx[1]},
+                {s.ctrl + C_WIDTHS, s.ctrl + C_WIDTHS + 1}, s, 2u};
+  hipLaunchKernelGGL(k_widths, dim3(2 * gr.widths), dim3(kThreads), 0, st, p);
   return hipGetLastError();
 }
 
@@ -2862,7 +2879,7 @@ hipError_t launch_compress(const Scratch& s, const Grids& gr, const float* x, co
 hipError_t launch_decompress(const Scratch& s, const Grids& gr, const uint8_t* c,
                              uint64_t c_bytes, float* x, uint64_t n_cap, hoszp_result* res,
                              hipStream_t st) {
-  hipError_t e = launch_widths(s, gr, 0, c, c_bytes, st);
+  hipError_t e = launch_widths(s, gr, c, c_bytes, st);
   if (e != hipSuccess) return e;
   DecodeParams p{c, c_bytes, x, n_cap, s, res};
   hipLaunchKernelGGL(k_decode<kDecompress>, dim3(gr.decode), dim3(kThreads), 0, st, p);
@@ -2871,7 +2888,7 @@ hipError_t launch_decompress(const Scratch& s, const Grids& gr, const uint8_t* c
 
 hipError_t launch_reduce(const Scratch& s, const Grids& gr, const uint8_t* c, uint64_t c_bytes,
                          bool variance, hoszp_result* res, hipStream_t st) {
-  hipError_t e = launch_widths(s, gr, 0, c, c_bytes, st);
+  hipError_t e = launch_widths(s, gr, c, c_bytes, st);
   if (e != hipSuccess) return e;
   DecodeParams p{c, c_bytes, nullptr, 0, s, res};
   if (variance)
@@ -2884,7 +2901,7 @@ hipError_t launch_reduce(const Scratch& s, const Grids& gr, const uint8_t* c, ui
 hipError_t launch_block_means(const Scratch& s, const Grids& gr, const uint8_t* c,
                               uint64_t c_bytes, double* means, uint64_t means_cap,
                               hoszp_result* res, hipStream_t st) {
-  hipError_t e = launch_widths(s, gr, 0, c, c_bytes, st);
+  hipError_t e = launch_widths(s, gr, c, c_bytes, st);
   if (e != hipSuccess) return e;
   DecodeParams p{c, c_bytes, nullptr, means_cap, s, res, means};
   hipLaunchKernelGGL(k_decode<kBlockMean>, dim3(gr.reduce), dim3(kReduceThreads), 0, st, p);
@@ -2901,7 +2918,7 @@ hipError_t launch_negate(const Scratch& s, const Grids& gr, const uint8_t* c, ui
 hipError_t launch_shift(const Scratch& s, const Grids& gr, const uint8_t* c, uint64_t c_bytes,
                         double scalar, int sign, uint8_t* out, uint64_t out_cap,
                         hoszp_result* res, hipStream_t st) {
-  hipError_t e = launch_widths(s, gr, 0, c, c_bytes, st);
+  hipError_t e = launch_widths(s, gr, c, c_bytes, st);
   if (e != hipSuccess) return e;
   NegateParams p{c, c_bytes, out, out_cap, s, res, scalar, sign, 0};
   hipLaunchKernelGGL(k_negate<kShift>, dim3(gr.negate), dim3(kThreads), 0, st, p);
@@ -2911,8 +2928,7 @@ hipError_t launch_shift(const Scratch& s, const Grids& gr, const uint8_t* c, uin
 hipError_t launch_add(const Scratch& s, const Grids& gr, const uint8_t* a, uint64_t a_bytes,
                       const uint8_t* b, uint64_t b_bytes, uint8_t* out, uint64_t out_cap,
                       hoszp_result* res, hipStream_t st, bool sub) {
-  hipError_t e = launch_widths(s, gr, 0, a, a_bytes, st);
-  if (e == hipSuccess) e = launch_widths(s, gr, 1, b, b_bytes, st);
+  hipError_t e = launch_widths2(s, gr, a, a_bytes, b, b_bytes, st);
   if (e != hipSuccess) return e;
   AddParams p{a, a_bytes, b, b_bytes, out, out_cap, s, res};
   if (sub)
@@ -2925,7 +2941,7 @@ hipError_t launch_add(const Scratch& s, const Grids& gr, const uint8_t* a, uint6
 hipError_t launch_mul(const Scratch& s, const Grids& gr, const uint8_t* c, uint64_t c_bytes,
                       MulScalar k, uint8_t* out, uint64_t out_cap, hoszp_result* res,
                       hipStream_t st) {
-  hipError_t e = launch_widths(s, gr, 0, c, c_bytes, st);
+  hipError_t e = launch_widths(s, gr, c, c_bytes, st);
   if (e != hipSuccess) return e;
   MulParams p{c, c_bytes, out, out_cap, k, s, res};
   hipLaunchKernelGGL(k_mul<kMulThreads>, dim3(gr.mul), dim3(kMulThreads), 0, st, p);
@@ -2935,8 +2951,7 @@ hipError_t launch_mul(const Scratch& s, const Grids& gr, const uint8_t* c, uint6
 hipError_t launch_bivar(const Scratch& s, const Grids& gr, bool covariance, const uint8_t* a,
                         uint64_t a_bytes, const uint8_t* b, uint64_t b_bytes, uint8_t* out,
                         uint64_t out_cap, hoszp_result* res, hipStream_t st) {
-  hipError_t e = launch_widths(s, gr, 0, a, a_bytes, st);
-  if (e == hipSuccess) e = launch_widths(s, gr, 1, b, b_bytes, st);
+  hipError_t e = launch_widths2(s, gr, a, a_bytes, b, b_bytes, st);
   if (e != hipSuccess) return e;
   BivarParams p{a, a_bytes, b, b_bytes, out, out_cap, s, res};
   if (covariance)
