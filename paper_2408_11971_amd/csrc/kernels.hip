@@ -1348,8 +1348,9 @@ __device__ __forceinline__ int32_t mean_fast(const uint32_t* sp, uint32_t w, uin
 
 // Fast path of a full segment (width 1..20) for the variance: E = sum e_j
 // (int32), E2 = sum e_j^2 (int64), D = delta total; G as for the mean.  With
-// G = 4 (w <= 8) every |e_j| <= 31 * 255, so the squares and their sum stay
-// below 2^31 and are formed on the 24-bit multiplier in 32 bits.
+// G = 4 (w <= 8) every |e_j| <= 32 * 255 = 8160, so each square is below
+// 2^26 and the 32 of them sum to at most 2 130 739 200 < 2^31: they are
+// formed on the 24-bit multiplier and summed in 32 bits.
 template <int G>
 __device__ __forceinline__ void var_fast(const uint32_t* sp, uint32_t w, uint32_t sw,
                                          bool first_seg, int32_t& E, int64_t& E2, int32_t& D) {
