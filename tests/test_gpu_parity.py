@@ -240,16 +240,62 @@ def test_malformed_streams(dev):
         out = torch.empty(hz.compress_bound(50000, 32), dtype=torch.uint8, device=dev)
         assert err_of(hz.mul, g, 2.0, out=out) == hz.ERR_FORMAT
         assert err_of(hz.add, g, gpu(c, dev), out=out) == hz.ERR_FORMAT
+        # the second operand is indexed by the other half of the same launch
+        assert err_of(hz.add, gpu(c, dev), g, out=out) == hz.ERR_FORMAT
+        assert err_of(hz.hadamard, gpu(c, dev), g, out=out) == hz.ERR_FORMAT
+        assert err_of(hz.covariance, gpu(c, dev), g) == hz.ERR_FORMAT
         xo = torch.empty(50000, dtype=torch.float32, device=dev)
         assert err_of(hz.decompress, g, out=xo) == hz.ERR_FORMAT
 
 
-def test_out_of_range_outlier_is_format_error(dev):
+def test_width_above_32_is_format_error(dev):
+    # n = 1000, L = 32: the width section is bytes 64..95; widths 16..19
+    # become 0, 0, 0, 128
     c = ref.compress(gaussian(1000, 3), 0.01, 32)
     c[80:84] = np.array([0x80000000], dtype=np.uint32).view(np.uint8)
     g = gpu(c, dev)
     assert err_of(hz.mean, g) == hz.ERR_FORMAT
     assert err_of(hz.variance, g) == hz.ERR_FORMAT
+
+
+def outlier_offset(n, L):
+    nb = (n + L - 1) // L
+    return ((64 + nb + 15) // 16) * 16
+
+
+def test_outlier_edges(dev):
+    """Blocks whose outlier and width let a bin reach the int32 limits take
+    the decoders' exact per-slot check: bins at +-(2^31 - 1) decode like the
+    oracle; an outlier raised so that one bin passes 2^31 - 1, or an outlier
+    of -2^31, is a format error (for the oracle too)."""
+    K = 2**31 - 1
+    rng = np.random.default_rng(12)
+    n = 5000
+    q = rng.integers(-3, 4, n).astype(np.int64)
+    ramp = np.array([0, 1, 2, 3, 4, 5, 5, 4, 3, 2, 1, 0] * 11)[:64]
+    q[:64] = K - 5 + ramp                   # block 0 starts at K - 5 and touches K
+    q[64:128] = -K + np.abs(q[64:128])      # blocks near -K, touching it
+    q[100] = -K
+    q = q.astype(np.int32)
+    for L in (32, 64):
+        c = ref.encode_bins(q, 0.5, L)
+        g = gpu(c, dev)
+        print(f"case outlier edges L={L}", flush=True)
+        assert hz.mean(g) == ref.mean(c)
+        assert hz.variance(g) == ref.variance(c)
+        assert np.array_equal(host(hz.decompress(g)), ref.decompress(c))
+        o = outlier_offset(n, L)
+        up = c.copy()
+        up[o:o + 4] = np.array([K - 4], dtype=np.int32).view(np.uint8)  # the bin K becomes K + 1
+        low = c.copy()
+        low[o:o + 4] = np.array([-2**31], dtype=np.int32).view(np.uint8)
+        for bad in (up, low):
+            with pytest.raises(ref.RefError):
+                ref.mean(bad)
+            gb = gpu(bad, dev)
+            assert err_of(hz.mean, gb) == hz.ERR_FORMAT
+            assert err_of(hz.variance, gb) == hz.ERR_FORMAT
+            assert err_of(hz.decompress, gb) == hz.ERR_FORMAT
 
 
 def test_add_mismatch_capacity_and_range(dev):
