@@ -450,16 +450,39 @@ __device__ __forceinline__ uint64_t lb_wait(uint64_t* st, uint64_t tile, uint64_
 }
 
 
-// Payload word offset of wave tile `tile` of a stream from its width
-// pre-pass.  Run by one whole wave; every lane gets the result.
-__device__ __forceinline__ uint64_t tile_offset(const TileIndex& ix, uint64_t tile) {
+// Streams of at most kDirectChunks chunks (up to 2^18 segments) skip the
+// width pre-pass's last step (its completion count and the last workgroup's
+// scan of the chunk totals): their consumers form a chunk's offset from the
+// chunk totals themselves, one inclusive scan over a wave, and check that the
+// totals fill the payload (which the pre-pass checks for larger streams).
+constexpr uint64_t kDirectChunks = 64;
+__device__ __forceinline__ uint64_t num_chunks(const Layout& g) {
+  return (g.nwtiles + kChunkTiles - 1) / kChunkTiles;
+}
+// From every lane's chunk total (0 past the last chunk): the offset of chunk
+// `chunk` (wave-uniform) and the check of the total.  Whole wave.
+__device__ __forceinline__ uint64_t direct_chunk_off(uint32_t cw, uint64_t chunk,
+                                                     uint64_t payload_words, uint32_t& bad) {
+  // a chunk holds at most 64 x 2048 words, so 64 of them sum below 2^23
+  const uint32_t x = wave_incl_scan(cw);
+  if (lane_of(x, 63) != payload_words) bad |= ST_FORMAT;
+  return chunk ? lane_of(x, int(chunk) - 1) : 0u;
+}
+
+// Payload word offset of wave tile `tile` of a stream (layout g) from its
+// width pre-pass.  Run by one whole wave; every lane gets the result.
+__device__ __forceinline__ uint64_t tile_offset(const TileIndex& ix, uint64_t tile, const Layout& g,
+                                                uint32_t& bad) {
   const int lane = threadIdx.x & 63;
   const uint64_t chunk = tile / kChunkTiles;
   const uint32_t r = uint32_t(tile % kChunkTiles);
+  const uint64_t nch = num_chunks(g);
+  const bool direct = nch <= kDirectChunks;
   // both loads issued before either is waited on (lanes past r load the
   // chunk's first word and drop it)
   const uint32_t t = ix.tile_words[chunk * kChunkTiles + (uint32_t(lane) < r ? lane : 0)];
-  const uint64_t c = ix.chunk_off[chunk];
+  uint64_t c = direct ? (uint32_t(lane) < nch ? ix.chunk_words[lane] : 0u) : ix.chunk_off[chunk];
+  if (direct) c = direct_chunk_off(uint32_t(c), chunk, g.payload_bytes / 4, bad);
   // a wave tile holds at most 64 x 32 words, so 63 of them sum below 2^17
   return c + wave_sum32(uint32_t(lane) < r ? t : 0u);
 }
@@ -845,6 +868,7 @@ __global__ void __launch_bounds__(kThreads) k_widths(WidthParams p) {
     __syncthreads();
   }
   latch(p.s, bad);
+  if (nchunks <= kDirectChunks) return;  // consumers scan the chunk totals themselves
   if (!finish_arrive_n(p.done[which], 1u, gsz, &s_flag)) return;
   // last workgroup: chunk counts -> chunk offsets, and the total check
   const uint64_t per = (nchunks + kThreads - 1) / kThreads;
@@ -1480,7 +1504,11 @@ __device__ __forceinline__ void meta_a(const Layout& g, const uint8_t* W, const 
   const uint64_t chunk = wt / kChunkTiles;
   const uint32_t r = uint32_t(wt % kChunkTiles);
   m.tw = (wt < nwt && uint32_t(lane) < r) ? ix.tile_words[chunk * kChunkTiles + lane] : 0u;
-  m.chunk_off = wt < nwt ? ix.chunk_off[chunk] : 0u;
+  const uint64_t nch = num_chunks(g);
+  if (nch <= kDirectChunks)  // every lane's chunk total, scanned in meta_b
+    m.chunk_off = (wt < nwt && uint32_t(lane) < nch) ? ix.chunk_words[lane] : 0u;
+  else
+    m.chunk_off = wt < nwt ? ix.chunk_off[chunk] : 0u;
 }
 
 template <int PF>
@@ -1501,8 +1529,14 @@ __device__ __forceinline__ void meta_b(const Layout& g, const uint32_t* S, const
   m.words = lane_of(x, 63);
   m.wmax = wave_max(w);
   m.outlier = a.outlier;
+  uint64_t cbase = a.chunk_off;
+  if (num_chunks(g) <= kDirectChunks) {
+    uint32_t b2 = 0;
+    cbase = direct_chunk_off(uint32_t(a.chunk_off), wt < nwt ? wt / kChunkTiles : 0u, payload_words, b2);
+    if (wt < nwt) bad |= b2;
+  }
   // a wave tile holds at most 64 x 32 words, so 63 of them sum below 2^17
-  m.base = a.chunk_off + wave_sum32(a.tw);
+  m.base = cbase + wave_sum32(a.tw);
   m.sw = (cnt > 0 && w > 0) ? S[seg] : 0u;
   if (m.base + m.words > payload_words) {
     bad |= ST_FORMAT;
@@ -1777,7 +1811,11 @@ __device__ __noinline__ bool block_prefix_range(const uint8_t* c, const Layout& 
                                                 uint32_t len, int64_t& lo, int64_t& hi) {
   const uint64_t seg0 = blk << g.spb_log2;
   const uint64_t wt = seg0 / kWaveSegs, chunk = wt / kChunkTiles;
-  uint64_t off = ix.chunk_off[chunk];
+  uint64_t off = 0;
+  if (num_chunks(g) <= kDirectChunks)
+    for (uint64_t k = 0; k < chunk; ++k) off += ix.chunk_words[k];
+  else
+    off = ix.chunk_off[chunk];
   for (uint64_t t = chunk * kChunkTiles; t < wt; ++t) off += ix.tile_words[t];
   for (uint64_t b = (wt * kWaveSegs) >> g.spb_log2; b < blk; ++b)
     off += min(uint64_t(c[g.off_w + b]), uint64_t(32)) * g.spb;
@@ -1989,11 +2027,19 @@ __global__ void __launch_bounds__(NT) k_add(AddParams p) {
     const uint64_t tile = uni64(s_ticket);
     if (tile >= ntiles) break;
     if (tid < 64) {
-      const uint64_t v = tile_offset(p.s.idx[0], (NT / kWaveSegs) * tile);
-      if (tid == 0) s_base_a = v;
+      uint32_t b2 = 0;
+      const uint64_t v = tile_offset(p.s.idx[0], (NT / kWaveSegs) * tile, g, b2);
+      if (tid == 0) {
+        s_base_a = v;
+        latch(p.s, b2);
+      }
     } else if (tid < 128) {
-      const uint64_t v = tile_offset(p.s.idx[1], (NT / kWaveSegs) * tile);
-      if (tid == 64) s_base_b = v;
+      uint32_t b2 = 0;
+      const uint64_t v = tile_offset(p.s.idx[1], (NT / kWaveSegs) * tile, gb, b2);
+      if (tid == 64) {
+        s_base_b = v;
+        latch(p.s, b2);
+      }
     }
     const uint64_t seg = tile * NT + tid;
     const bool active = seg < g.nseg;
@@ -2258,8 +2304,12 @@ __global__ void __launch_bounds__(NT) k_mul(MulParams p) {
     const uint64_t tile = uni64(s_ticket);
     if (tile >= ntiles) break;
     if (tid < 64) {
-      const uint64_t v = tile_offset(p.s.idx[0], (NT / kWaveSegs) * tile);
-      if (tid == 0) s_base = v;
+      uint32_t b2 = 0;
+      const uint64_t v = tile_offset(p.s.idx[0], (NT / kWaveSegs) * tile, g, b2);
+      if (tid == 0) {
+        s_base = v;
+        latch(p.s, b2);
+      }
     }
     const uint64_t seg = tile * NT + tid;
     const bool active = seg < g.nseg;
@@ -2503,11 +2553,19 @@ __global__ void __launch_bounds__(NT) k_bivar(BivarParams p) {
     const uint64_t tile = uni64(s_ticket);
     if (tile >= ntiles) break;
     if (tid < 64) {
-      const uint64_t v = tile_offset(p.s.idx[0], (NT / kWaveSegs) * tile);
-      if (tid == 0) s_base_a = v;
+      uint32_t b2 = 0;
+      const uint64_t v = tile_offset(p.s.idx[0], (NT / kWaveSegs) * tile, g, b2);
+      if (tid == 0) {
+        s_base_a = v;
+        latch(p.s, b2);
+      }
     } else if (tid < 128) {
-      const uint64_t v = tile_offset(p.s.idx[1], (NT / kWaveSegs) * tile);
-      if (tid == 64) s_base_b = v;
+      uint32_t b2 = 0;
+      const uint64_t v = tile_offset(p.s.idx[1], (NT / kWaveSegs) * tile, gb, b2);
+      if (tid == 64) {
+        s_base_b = v;
+        latch(p.s, b2);
+      }
     }
     const uint64_t seg = tile * NT + tid;
     const bool active = seg < g.nseg;
