@@ -84,6 +84,21 @@ def test_multi_tile_ragged(dev, n, L):
     check_all_ops(x, y, synth.rel_eb(x, 1e-3), L, dev)
 
 
+@pytest.mark.parametrize("n", [64 * 4096 * 32, 64 * 4096 * 32 + 1])
+def test_direct_chunk_boundary(dev, n):
+    """Streams of up to 64 chunks of 64 wave tiles (2^23 values at 32 slots a
+    segment) get their chunk offsets from the consumers' own scan, larger
+    ones from the width pre-pass's scan: both sides of the boundary (and of
+    it at every block size, as segments do not depend on L) match the
+    oracle."""
+    x = synth.sinusoid_1d(n, seed=5)
+    y = synth.sinusoid_1d(n, seed=6)
+    eb = synth.rel_eb(x, 1e-3)
+    for L in (32, 256):
+        print(f"case direct-chunk boundary n={n} L={L}", flush=True)
+        check_all_ops(x, y, eb, L, dev, scalars=(3.14,))
+
+
 @pytest.mark.parametrize("rel", [1e-2, 1e-3, 1e-4])
 def test_config_1d_full(dev, rel):
     """2^20-element sum of 8 sinusoids plus noise, block 32."""
