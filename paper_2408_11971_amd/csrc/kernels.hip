@@ -1881,12 +1881,12 @@ __global__ void __launch_bounds__(kThreads) k_negate(NegateParams p) {
   const uint64_t w_end = g.off_w + g.nb, o_end = g.off_o + 4 * g.nb, s_end = g.off_s + 4 * g.nseg;
   // Each thread moves kNegUnroll chunks per round, all loaded before any is
   // written (no lane condition on the loads: past the end a thread reloads the
-  // last chunk and drops it), so the loads of a round are in flight together.
+  // last chunk and drops it), so the loads of a round are in flight together;
+  // a round's loads are issued before the previous round's stores, so they
+  // are in flight while that round is processed and written.
   constexpr int kNegUnroll = 4;
-  for (uint64_t k0 = kbeg + uint64_t(blockIdx.x) * kThreads + tid; k0 < kend;
-       k0 += kNegUnroll * stride) {
-    uint4 v[kNegUnroll];
-    uint32_t wq[kNegUnroll];  // the aligned width word holding the chunk's blocks
+  // one round's chunks, and for each the aligned width word of its blocks
+  auto load_round = [&](uint64_t k0, uint4* v, uint32_t* wq) {
 #pragma unroll
     for (int u = 0; u < kNegUnroll; ++u) {
       const uint64_t k = min(k0 + uint64_t(u) * stride, kend - 1);
@@ -1903,6 +1903,15 @@ __global__ void __launch_bounds__(kThreads) k_negate(NegateParams p) {
         wq[u] = W32[b0 >> 2];
       }
     }
+  };
+  uint4 v[kNegUnroll];
+  uint32_t wq[kNegUnroll];
+  uint64_t k0 = kbeg + uint64_t(blockIdx.x) * kThreads + tid;
+  if (k0 < kend) load_round(k0, v, wq);
+  for (; k0 < kend; k0 += kNegUnroll * stride) {
+    uint4 nv[kNegUnroll];
+    uint32_t nwq[kNegUnroll];
+    load_round(k0 + kNegUnroll * stride, nv, nwq);  // (clamped to the last chunk past the end)
 #pragma unroll
     for (int u = 0; u < kNegUnroll; ++u) {
       const uint64_t k = k0 + uint64_t(u) * stride;
@@ -1964,6 +1973,11 @@ __global__ void __launch_bounds__(kThreads) k_negate(NegateParams p) {
         }
       }
       dst[k] = make_uint4(wd[0], wd[1], wd[2], wd[3]);
+    }
+#pragma unroll
+    for (int u = 0; u < kNegUnroll; ++u) {
+      v[u] = nv[u];
+      wq[u] = nwq[u];
     }
   }
   // the last partial chunk (payload words only): one thread
