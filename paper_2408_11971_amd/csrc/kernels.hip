@@ -6,8 +6,8 @@
 // payload offsets are prefix sums of per-segment widths:
 //   - decoders (mean, variance, decompress) work per wave on tiles of 64
 //     segments and get offsets from a width pre-pass (k_widths) that reads
-//     only the width section and stores per-tile word counts and per-chunk
-//     prefixes;
+//     only the width section and stores per-tile word counts, per-chunk
+//     totals and (for streams of more than 64 chunks) per-chunk prefixes;
 //   - encoders (compress, add, mul, batch) work per workgroup on tiles of
 //     NT segments (1024 threads) and produce offsets with a single-pass
 //     decoupled look-back over per-tile word counts, with tiles taken from an
@@ -16,8 +16,8 @@
 // Payload words are staged in LDS as big-endian values (one byte swap per
 // word), so a w-bit field at bit p of a segment is one funnel shift
 // (v_alignbit) of two neighbouring LDS words.  Wave-level sums and minima are
-// ds_swizzle butterflies and wave scans DPP row shifts and broadcasts, so no
-// lane-index registers stay live in the kernels' loops.
+// ds_swizzle butterflies, wave maxima and scans DPP row shifts and
+// broadcasts, so no lane-index registers stay live in the kernels' loops.
 //
 // Every operation ends in one kernel whose last workgroup to finish writes
 // the caller's result record and returns the context's counters to zero, so
@@ -463,7 +463,7 @@ __device__ __forceinline__ uint64_t num_chunks(const Layout& g) {
 // `chunk` (wave-uniform) and the check of the total.  Whole wave.
 __device__ __forceinline__ uint64_t direct_chunk_off(uint32_t cw, uint64_t chunk,
                                                      uint64_t payload_words, uint32_t& bad) {
-  // a chunk holds at most 64 x 2048 words, so 64 of them sum below 2^23
+  // a chunk holds at most 64 x 2048 words, so 64 of them sum to at most 2^23
   const uint32_t x = wave_incl_scan(cw);
   if (lane_of(x, 63) != payload_words) bad |= ST_FORMAT;
   return chunk ? lane_of(x, int(chunk) - 1) : 0u;
